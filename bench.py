@@ -1,0 +1,201 @@
+"""Throughput of the D3Q19 Shan-Chen step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+A step is one full time step of the method (streaming, moments, psi, force
+gather, forcing, collision) over the whole box; the interface diagnostics
+(minimum radius, mass, momentum) run every 100 steps inside the timed
+region.  The workload is a 256 x 256 x 1024 periodic box (67.1 M nodes)
+holding a perturbed ligament of radius 64, D3Q19 MRT, Guo forcing, G = -5,
+float32 shifted storage; the same box is also run in float64.
+
+Prints one JSON line: MLUPS (million lattice-node updates per second),
+the fraction of the HBM roofline reached by the step kernel, and the float64
+oracle timed on the host cores on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "ligament_256x256x1024_mrt_f32"
+METRIC = "MLUPS & % HBM peak, D3Q19 Shan-Chen FP32 vs FP64; adjoint/forward cost ratio"
+DIAG_EVERY = 100
+# Algorithmic bytes per node and step: 19 populations read + 19 written.
+BYTES_PER_NODE = {"f32": 19 * 2 * 4, "f64": 19 * 2 * 8}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("lbsc_device.hip", "lbsc_api.hip"):
+        with open(os.path.join(ROOT, "paper_1905_09554_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    runs, or None when absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (workload, precision))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_gpu(rho0, info, precision, steps, warmup):
+    import torch
+    from paper_1905_09554_amd import lbsc, tuning
+
+    nz, ny, nx = rho0.shape
+    n = rho0.size
+    prm = lbsc.make_params(nx, ny, nz, collision=info["collision"], precision=precision,
+                           G=info["G"], tau=info["tau"], rho_ref=1.0)
+    sim = lbsc.Simulation(rho0, prm, device="cuda:0")
+    tune = tuning.apply(sim, prm)
+    stream = sim.stream
+    rv, rl = info["rho_v"], info["rho_l"]
+
+    sim.step(warmup)
+    sim.diagnostics(rv, rl)
+    torch.cuda.synchronize()
+
+    # Whole-job timing: steps plus diagnostics every DIAG_EVERY steps.
+    t0 = time.perf_counter()
+    done = 0
+    diag = None
+    while done < steps:
+        k = min(DIAG_EVERY, steps - done)
+        sim.step(k)
+        done += k
+        if done % DIAG_EVERY == 0 or done == steps:
+            diag = sim.diagnostics(rv, rl)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+
+    # Step-kernel duration: HIP events on the stream the kernels run on.
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    kreps = max(10, min(steps, 200))
+    with torch.cuda.stream(stream):
+        ev0.record(stream)
+        sim.step(kreps)
+        ev1.record(stream)
+    ev1.synchronize()
+    per_launch_s = ev0.elapsed_time(ev1) / 1e3 / kreps
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+
+    alg = BYTES_PER_NODE[precision] * n
+    achieved = alg / per_launch_s / 1e9
+    traffic = measured_traffic(WORKLOAD, precision)
+    return {
+        "mlups": n * steps / wall / 1e6,
+        "ms_per_step": wall / steps * 1e3,
+        "kernel_ms": per_launch_s * 1e3,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "tuning": tune,
+        "r_min": diag["r_min"] if diag else None,
+        "mass": diag["mass"] if diag else None,
+    }
+
+
+def cpu_baseline(rho0, info, nz_sample=16, steps=12):
+    """The float64 oracle on the host: the first nz_sample planes of the same
+    input as a periodic slab, `steps` steps, reported in MLUPS."""
+    import torch
+    from oracle import lbm
+
+    torch.set_num_threads(min(16, os.cpu_count() or 1))
+    sample = rho0[:nz_sample].copy()
+    p = lbm.Params(G=info["G"], tau=info["tau"], collision=info["collision"])
+    f = lbm.init_rest(torch.from_numpy(sample))
+    f = lbm.step(f, p)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f = lbm.step(f, p)
+    dt = time.perf_counter() - t0
+    return {"value": round(sample.size * steps / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": "%dx%dx%d periodic slab (first %d planes of the benchmark input), "
+                      "%s float64, %d steps, %.1f s" % (sample.shape[2], sample.shape[1],
+                                                        nz_sample, nz_sample, info["collision"],
+                                                        steps, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the float64 figure")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (the step is single-GPU; see the design notes "
+              "for how it would shard); got --gpus %d" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import lbm_inputs
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+
+    rho0, info = lbm_inputs.workload_density(WORKLOAD)
+    print("workload %s: %d nodes" % (WORKLOAD, rho0.size), file=sys.stderr, flush=True)
+    f32 = run_gpu(rho0, info, "f32", args.steps, args.warmup)
+    print("f32 done: %.0f MLUPS" % f32["mlups"], file=sys.stderr, flush=True)
+    f64 = None
+    if not args.no_fp64:
+        f64 = run_gpu(rho0, info, "f64", max(50, args.steps // 2), args.warmup)
+        print("f64 done: %.0f MLUPS" % f64["mlups"], file=sys.stderr, flush=True)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(rho0, info)
+
+    nz, ny, nx = rho0.shape
+    line = {
+        "metric": METRIC,
+        "value": round(f32["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f32["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "nx": nx, "ny": ny, "nz": nz, "nodes": rho0.size,
+                   "collision": info["collision"], "forcing": "guo", "G": info["G"],
+                   "tau": info["tau"], "storage": "f32 shifted, rho_ref 1.0",
+                   "R": info["R"], "kR_eff": round(info["kR_eff"], 4),
+                   "diagnostics_every": DIAG_EVERY, "tuning": f32["tuning"]},
+        "roofline": f32["roofline"],
+        "kernel_ms": round(f32["kernel_ms"], 4),
+        "hbm_frac_alg": round(f32["mlups"] * 1e6 * BYTES_PER_NODE["f32"] / 1e9 / HBM_PEAK_GBS, 4),
+        "cpu_baseline": cpu,
+    }
+    if f64:
+        line["fp64"] = {"value": round(f64["mlups"], 1), "unit": "MLUPS", "dtype": "f64",
+                        "ms_per_step": round(f64["ms_per_step"], 4),
+                        "kernel_ms": round(f64["kernel_ms"], 4), "roofline": f64["roofline"],
+                        "tuning": f64["tuning"]}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,170 @@
+/*
+ * lbsc -- D3Q19 pseudo-potential (Shan-Chen) lattice Boltzmann step on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The method is the one of Chiappini, Xue, Falcucci and Sbragaglia,
+ * "Hydrodynamic behavior of the Pseudo-Potential lattice Boltzmann method for
+ * interfacial flows" (arXiv:1905.09554), Sec. 2:
+ *   - lattice Boltzmann equation with D3Q19 populations f_a(x, t),
+ *     collide at x then stream to x + c_a                    (Eq. LBE)
+ *   - SRT (BGK, rate 1/tau) or MRT (M^-1 Lambda M) collision (collision cases)
+ *   - equilibrium f^eq of Eq. local_eq, moments of Eq. momentum
+ *   - Shan-Chen force F = -G psi(x) sum_a w_a psi(x + c_a) c_a  (Eq. SC_force)
+ *     with psi = rho0 (1 - exp(-rho / rho0))
+ *   - forcing: Guo-like, u^b = u + F/(2 rho) (Eq. barycentric) plus the Guo
+ *     source term, or the SRT velocity shift u' = u + tau F / rho (Eq. vel_shift)
+ *   - equation of state P = rho c_s^2 + c_s^2 G psi^2 / 2    (Eq. EOS_SC)
+ * on a fully periodic box L_x x L_y x L_z holding a liquid ligament (Sec. 3),
+ * with the minimum ligament radius as diagnostic (Sec. 4, Fig. 5).
+ *
+ * Conventions for every call
+ *   - Every call returns an lbsc_status (0 on success) and never aborts.
+ *   - Host arrays are owned by the caller and copied.  Device memory is owned
+ *     by the caller and borrowed: the library never allocates or frees device
+ *     memory.  One caller buffer of lbsc_state_bytes() bytes holds the whole
+ *     state (two population lattices plus a small reduction area).
+ *   - Arrays are C order [z][y][x] (x fastest); populations [a][z][y][x].
+ *   - Work is queued on the caller's HIP stream, asynchronously, unless the
+ *     call says it synchronises.
+ *   - Outputs are float64 whatever the storage precision.
+ *   - On error, lbsc_last_error() returns a message; a HIP error maps to
+ *     LBSC_EHIP with the HIP error string in the message.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef LBSC_H
+#define LBSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbsc_ctx lbsc_ctx;
+
+typedef enum lbsc_status {
+  LBSC_OK = 0,
+  LBSC_EINVAL = -1,     /* invalid argument: parameters, sizes, input field */
+  LBSC_ENOMEM = -2,     /* host allocation failed */
+  LBSC_EHIP = -3,       /* a HIP runtime call or kernel launch failed */
+  LBSC_ENONFINITE = -4, /* the state holds NaN or Inf (diagnostics found it) */
+  LBSC_ESTATE = -5      /* call not valid in the context's current state */
+} lbsc_status;
+
+/* Collision operator (Sec. 2, the SRT and MRT cases of Omega_coll). */
+enum { LBSC_BGK = 0, LBSC_MRT = 1 };
+/* Forcing: Guo-like with barycentric velocity (Eq. barycentric) or the SRT
+ * velocity shift (Eq. vel_shift; BGK only). */
+enum { LBSC_FORCING_GUO = 0, LBSC_FORCING_SHIFT = 1 };
+/* Storage precision: float64 populations, or float32 populations stored
+ * shifted as g_a = f_a - w_a rho_ref with float32 arithmetic. */
+enum { LBSC_F64 = 0, LBSC_F32_SHIFTED = 1 };
+
+typedef struct lbsc_params {
+  int32_t nx, ny, nz;  /* periodic box, x fastest; each >= 1, nx <= 1024      */
+  int32_t collision;   /* LBSC_BGK or LBSC_MRT                                */
+  int32_t forcing;     /* LBSC_FORCING_GUO or LBSC_FORCING_SHIFT (BGK only)   */
+  int32_t precision;   /* LBSC_F64 or LBSC_F32_SHIFTED                        */
+  double G;            /* interaction strength G_0 of Eq. SC_force (finite)   */
+  double psi_rho0;     /* rho_0 of psi (the paper fixes 1.0); > 0             */
+  double tau;          /* BGK relaxation time; MRT shear rate is 1/tau; > 0.5 */
+  double s_bulk;       /* MRT rate of the energy (bulk) row, in (0, 2)        */
+  double s_ghost;      /* MRT rate of the non-hydrodynamic rows, in (0, 2)    */
+  double rho_ref;      /* shift of the float32 storage (ignored for F64)      */
+} lbsc_params;
+
+/* Result of lbsc_interface_diagnostics. */
+typedef struct lbsc_diag {
+  double mass;     /* sum_x rho                                              */
+  double mom[3];   /* sum_x (j + F/2) = sum_x rho u^b                         */
+  double r_min;    /* min_z r(z), r(z) = sqrt(A(z)/pi)                        */
+  int32_t z_argmin;/* smallest z at which r(z) = r_min                        */
+  int32_t reserved;
+} lbsc_diag;
+
+/* Kernel launch shape and population layout; the autotuner picks these.
+ * threads, z_chunk, block_y: 0 means the default; pop_pad < 0 means the
+ * default.  Changing pop_pad re-lays the state out in place (same values). */
+typedef struct lbsc_tuning {
+  int32_t threads;     /* work-group size of the fused step: 256, 512, 1024   */
+  int32_t z_chunk;     /* planes marched per work-group (>= 1)                */
+  int32_t xcd_remap;   /* 1: map neighbouring tiles onto one XCD (L2), 0: off */
+  int32_t block_y;     /* rows per tile; 0 = as many as the work-group holds  */
+  int32_t pop_pad;     /* extra elements between population arrays, <= 65536 */
+} lbsc_tuning;
+
+/* Bytes of device memory a context with these parameters needs: two
+ * population lattices of 19 arrays of nx * ny * nz values in the storage
+ * precision (each array padded by up to 65536 elements so the arrays do not
+ * share HBM channels), plus a reduction area.  Returns 0 for invalid
+ * parameters. */
+size_t lbsc_state_bytes(const lbsc_params* p);
+
+/* Creates a context and sets the initial state f_a(x) = w_a rho0(x) (zero
+ * momentum; in float32 storage g_a = w_a (rho0 - rho_ref)).
+ *   rho0_host  nx*ny*nz float64 densities, host memory, copied; every value
+ *              must be finite and > 0.
+ *   dev_buf    device buffer of dev_bytes >= lbsc_state_bytes(p) bytes,
+ *              256-byte aligned, borrowed for the context's lifetime.
+ *   hip_stream hipStream_t to queue work on; NULL is the default stream.
+ * Initial geometry: Sec. 3 (perturbed cylinder) with densities from
+ * flat-interface runs.  Synchronises the stream before returning. */
+int lbsc_init_fields(lbsc_ctx** out, const lbsc_params* p, const double* rho0_host,
+                     void* dev_buf, size_t dev_bytes, void* hip_stream);
+
+/* Advances the state by nsteps >= 0 time steps (Eq. LBE with the force of
+ * Eq. SC_force), asynchronously on the context's stream. */
+int lbsc_step(lbsc_ctx* c, int64_t nsteps);
+
+/* Number of steps taken since the state was set. */
+int64_t lbsc_step_count(const lbsc_ctx* c);
+
+/* Moments of the current state into caller DEVICE buffers (float64):
+ *   rho_dev  N values, rho = sum_a f_a (Eq. momentum); required
+ *   u_dev    3N values [3][z][y][x], barycentric velocity u^b (Eq. barycentric),
+ *            or NULL
+ *   p_dev    N values, pressure of Eq. EOS_SC, or NULL
+ * Asynchronous on the context's stream. */
+int lbsc_compute_moments(lbsc_ctx* c, double* rho_dev, double* u_dev, double* p_dev);
+
+/* Interface diagnostics of the current state (Sec. 4, minimum ligament
+ * radius): liquid area per z-slice A(z) = sum_{x,y} clamp((rho - rho_v) /
+ * (rho_l - rho_v), 0, 1), r(z) = sqrt(A(z)/pi), r_min and its z; total mass
+ * and momentum.  All sums in float64 with a fixed reduction order (bitwise
+ * reproducible).  r_of_z_host: nz doubles or NULL.  Synchronises the stream.
+ * Returns LBSC_ENONFINITE if the mass is not finite. */
+int lbsc_interface_diagnostics(lbsc_ctx* c, double rho_v, double rho_l, lbsc_diag* out,
+                               double* r_of_z_host);
+
+/* Copies the post-streaming populations f_a(x) of the current time step to
+ * host memory: 19*N values [a][z][y][x] in the storage precision (float64 f,
+ * or float32 g = f - w rho_ref), bytes = 19*N*size.  *step receives the step
+ * counter (may be NULL).  Synchronises the stream. */
+int lbsc_get_state(lbsc_ctx* c, void* host, size_t bytes, int64_t* step);
+
+/* Replaces the state by populations in the layout of lbsc_get_state and sets
+ * the step counter; resuming from a saved state is bitwise identical to an
+ * uninterrupted run.  Synchronises the stream. */
+int lbsc_set_state(lbsc_ctx* c, const void* host, size_t bytes, int64_t step);
+
+/* Overrides the launch shape of the fused step (see lbsc_tuning). */
+int lbsc_set_tuning(lbsc_ctx* c, const lbsc_tuning* t);
+int lbsc_get_tuning(const lbsc_ctx* c, lbsc_tuning* t);
+
+/* Lattice of the library: velocities c[19][3] (cx, cy, cz) and weights w[19]
+ * in the population order used by lbsc_get_state.  Either may be NULL. */
+void lbsc_lattice(int32_t* c, double* w);
+
+/* Destroys a context (NULL is allowed); the device buffer is not freed. */
+void lbsc_destroy(lbsc_ctx* c);
+
+/* Message of the last error on this context; with c == NULL, the last error
+ * of a failed lbsc_init_fields on this thread. */
+const char* lbsc_last_error(const lbsc_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBSC_H */

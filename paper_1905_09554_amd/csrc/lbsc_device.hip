@@ -1,0 +1,821 @@
+// Device code of the D3Q19 pseudo-potential lattice Boltzmann step for gfx950.
+//
+// Method (arXiv:1905.09554, Sec. 2): populations f_a stream and collide
+// (Eq. LBE); moments by Eq. momentum; pseudo-potential psi = rho0 (1 -
+// exp(-rho/rho0)); Shan-Chen force of Eq. SC_force; Guo-like forcing with the
+// barycentric velocity of Eq. barycentric (plus the Guo source term), or the
+// SRT velocity shift of Eq. vel_shift; SRT (BGK) or MRT collision; equation of
+// state Eq. EOS_SC.
+//
+// Storage: structure of arrays, population a of node (x, y, z) at
+// lat[a * ps + (z * ny + y) * nx + x], with a population stride ps >= n that
+// is padded so the 19 streams do not fall on the same HBM channels.  A
+// lattice holds post-collision values
+// at their own node ("pull" layout): the post-streaming population of x is
+// f_a(x) = lat[a][x - c_a], so the step reads with +-1 offsets and writes
+// aligned.  In float32 storage the values are shifted, g_a = f_a - w_a rho_ref,
+// and every formula below is written for g (rho_ref = 0 gives plain f).
+//
+// The hot kernel fuses streaming, moments, psi, the force gather, forcing
+// and collision.  A work-group owns full x-rows [y0, y0 + by) and marches a
+// chunk of z planes.  For each plane it pulls the populations of its tile
+// plus one halo row on each side, reduces them to psi and keeps psi in a
+// ring of four LDS planes; the interior populations stay in registers for the
+// collision one plane later.  Each node therefore reads its 19 populations
+// from HBM once and writes 19; the halo rows are re-reads that hit L2 when
+// the neighbouring tile (placed on the same XCD) has just loaded them.
+#include "lbsc_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+namespace lbsc {
+namespace {
+
+// Compile-time loop: calls f(std::integral_constant<int, I>) for I = 0..N-1,
+// so every index below is a constant and per-node arrays live in registers.
+template <class F, int... I>
+__host__ __device__ inline void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__host__ __device__ inline void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// ------------------------------------------------------------------ lattice
+// D3Q19: rest, six axis links, twelve face diagonals; opposite pairs adjacent.
+constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+template <class R>
+__host__ __device__ constexpr R weight(int a) {
+  return a == 0 ? R(1) / R(3) : (a < 7 ? R(1) / R(18) : R(1) / R(36));
+}
+
+// d'Humieres et al. (2002) D3Q19 moment basis, row i evaluated at velocity a.
+// Rows: rho, e, eps, jx, qx, jy, qy, jz, qz, 3pxx, 3pixx, pww, piww, pxy,
+// pyz, pxz, mx, my, mz.
+__host__ __device__ constexpr int mrt_entry(int i, int a) {
+  const int x = CX[a], y = CY[a], z = CZ[a];
+  const int c2 = x * x + y * y + z * z;
+  switch (i) {
+    case 0: return 1;
+    case 1: return 19 * c2 - 30;
+    case 2: return (21 * c2 * c2 - 53 * c2 + 24) / 2;
+    case 3: return x;
+    case 4: return (5 * c2 - 9) * x;
+    case 5: return y;
+    case 6: return (5 * c2 - 9) * y;
+    case 7: return z;
+    case 8: return (5 * c2 - 9) * z;
+    case 9: return 3 * x * x - c2;
+    case 10: return (3 * c2 - 5) * (3 * x * x - c2);
+    case 11: return y * y - z * z;
+    case 12: return (3 * c2 - 5) * (y * y - z * z);
+    case 13: return x * y;
+    case 14: return y * z;
+    case 15: return x * z;
+    case 16: return (y * y - z * z) * x;
+    case 17: return (z * z - x * x) * y;
+    default: return (x * x - y * y) * z;
+  }
+}
+
+// Squared row norms sum_a M_ia^2 (rows are orthogonal, so M^-1 = M^T D^-1).
+__host__ __device__ constexpr int mrt_norm(int i) {
+  int s = 0;
+  for (int a = 0; a < Q; ++a) s += mrt_entry(i, a) * mrt_entry(i, a);
+  return s;
+}
+
+// Rate class of a row: 0 conserved, 1 bulk, 2 shear, 3 ghost.
+__host__ __device__ constexpr int mrt_class(int i) {
+  return (i == 0 || i == 3 || i == 5 || i == 7) ? 0
+         : (i == 1) ? 1
+         : (i == 9 || i == 11 || i == 13 || i == 14 || i == 15) ? 2
+                                                                  : 3;
+}
+
+template <class R>
+struct Phys {
+  R G, psi_rho0, inv_psi_rho0, tau, omega, s_bulk, s_ghost, rho_ref;
+};
+
+template <class R>
+__host__ __device__ inline Phys<R> make_phys(const StepArgs& a) {
+  Phys<R> p;
+  p.G = R(a.G);
+  p.psi_rho0 = R(a.psi_rho0);
+  p.inv_psi_rho0 = R(1.0 / a.psi_rho0);
+  p.tau = R(a.tau);
+  p.omega = R(a.omega);
+  p.s_bulk = R(a.s_bulk);
+  p.s_ghost = R(a.s_ghost);
+  p.rho_ref = R(a.rho_ref);
+  return p;
+}
+
+__device__ inline double psi_of(double rho, double rho0, double inv_rho0) {
+  return -rho0 * expm1(-rho * inv_rho0);
+}
+__device__ inline float psi_of(float rho, float rho0, float inv_rho0) {
+  return -rho0 * expm1f(-rho * inv_rho0);
+}
+
+// ---------------------------------------------------------------- collision
+// Error-free sum of two floats (Knuth's TwoSum): a + b = s + e exactly.
+__device__ inline void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bp = s - a;
+  e = (a - (s - bp)) + (b - bp);
+}
+
+// In-place collision of one node.  f holds the post-streaming populations
+// (shifted by w rho_ref), F the Shan-Chen force at the node.
+//
+// Float32 storage gets three numerical safeguards that are exact identities
+// in real arithmetic (so the method is unchanged):
+//  * the shifted density sum is compensated (TwoSum), and rho - rho_ref is
+//    taken from that sum, never from rho - rho_ref;
+//  * momenta are summed over differences of opposite populations, which are
+//    nearly equal and subtract with little or no rounding;
+//  * the collision is applied as an increment D (f* = f + D) whose mass sum
+//    is forced to 0 and momentum sum to F through the rest and axis
+//    populations.  Without this, the rounding of the equilibrium repeats
+//    with the same sign at slowly moving interface nodes and feeds the
+//    Plateau-Rayleigh mode as a systematic mass and momentum source.
+template <class R, int COLL, int FORC>
+__device__ inline void collide(R (&f)[Q], R Fx, R Fy, R Fz, const Phys<R>& k) {
+  constexpr bool kF32 = sizeof(R) == 4;
+  R s;
+  if constexpr (kF32) {
+    float acc = f[0], comp = 0.f;
+    static_for<Q - 1>([&](auto ac) {
+      constexpr int a = decltype(ac)::value + 1;
+      float t, e;
+      two_sum(acc, f[a], t, e);
+      acc = t;
+      comp += e;
+    });
+    s = acc + comp;
+  } else {
+    s = R(0);
+    static_for<Q>([&](auto ac) { s += f[decltype(ac)::value]; });
+  }
+  // Opposite pairs are (1,2), (3,4), ..., (17,18).
+  R jx = R(0), jy = R(0), jz = R(0);
+  static_for<(Q - 1) / 2>([&](auto pc) {
+    constexpr int a = 2 * decltype(pc)::value + 1;
+    const R d = f[a] - f[a + 1];
+    if constexpr (CX[a] != 0) jx += R(CX[a]) * d;
+    if constexpr (CY[a] != 0) jy += R(CY[a]) * d;
+    if constexpr (CZ[a] != 0) jz += R(CZ[a]) * d;
+  });
+  const R drho = s;
+  const R rho = k.rho_ref + s;
+  const R inv_rho = R(1) / rho;
+  // Equilibrium velocity: barycentric (Guo) or shifted by tau F / rho (SRT).
+  const R fs = (FORC == kGuo) ? R(0.5) : k.tau;
+  const R ux = (jx + fs * Fx) * inv_rho;
+  const R uy = (jy + fs * Fy) * inv_rho;
+  const R uz = (jz + fs * Fz) * inv_rho;
+  const R uu15 = R(1.5) * (ux * ux + uy * uy + uz * uz);
+  const R uF = ux * Fx + uy * Fy + uz * Fz;
+
+  R D[Q];
+  if constexpr (COLL == kBGK) {
+    const R om = k.omega;
+    const R src_fac = R(1) - R(0.5) * om;
+    static_for<Q>([&](auto ac) {
+      constexpr int a = decltype(ac)::value;
+      const R w = weight<R>(a);
+      R cu = R(0), cF = R(0);
+      if constexpr (CX[a] != 0) { cu += R(CX[a]) * ux; cF += R(CX[a]) * Fx; }
+      if constexpr (CY[a] != 0) { cu += R(CY[a]) * uy; cF += R(CY[a]) * Fy; }
+      if constexpr (CZ[a] != 0) { cu += R(CZ[a]) * uz; cF += R(CZ[a]) * Fz; }
+      const R geq = w * drho + w * rho * (R(3) * cu + R(4.5) * cu * cu - uu15);
+      R d = om * (geq - f[a]);
+      if constexpr (FORC == kGuo) d += src_fac * (w * (R(3) * (cF - uF) + R(9) * cu * cF));
+      D[a] = d;
+    });
+  } else {
+    // MRT: f* = f - M^T D^-1 [Lambda (M f - m_eq) - (I - Lambda/2) M S],
+    // using M^-1 = M^T D^-1 (orthogonal rows, D their squared norms).  The
+    // equilibrium moments m_eq = M f^eq(rho, u^b) and the source moments M S
+    // of the quadratic D3Q19 equilibrium and the Guo term have closed forms,
+    // so only M f is transformed numerically.  With shifted storage
+    // (g = f - w rho_ref) the rows e and eps see M (w rho_ref) = (-11, 3)
+    // rho_ref, which is folded into their equilibria through drho.
+    const R ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
+    const R usq = ux2 + uy2 + uz2;
+    const R pxx = R(2) * ux2 - uy2 - uz2;       // 3 p_xx / rho
+    const R pww = uy2 - uz2;                     // p_ww / rho
+    const R sxx = R(2) * ux * Fx - uy * Fy - uz * Fz;
+    const R sww = uy * Fy - uz * Fz;
+    R meq[Q], msrc[Q];
+    static_for<Q>([&](auto ic) { meq[decltype(ic)::value] = R(0); msrc[decltype(ic)::value] = R(0); });
+    meq[1] = R(-11) * drho + R(19) * rho * usq;  msrc[1] = R(38) * uF;
+    meq[2] = R(3) * drho - R(5.5) * rho * usq;   msrc[2] = R(-11) * uF;
+    meq[4] = R(-2.0 / 3.0) * rho * ux;           msrc[4] = R(-2.0 / 3.0) * Fx;
+    meq[6] = R(-2.0 / 3.0) * rho * uy;           msrc[6] = R(-2.0 / 3.0) * Fy;
+    meq[8] = R(-2.0 / 3.0) * rho * uz;           msrc[8] = R(-2.0 / 3.0) * Fz;
+    meq[9] = rho * pxx;                          msrc[9] = R(2) * sxx;
+    meq[10] = R(-0.5) * rho * pxx;               msrc[10] = -sxx;
+    meq[11] = rho * pww;                         msrc[11] = R(2) * sww;
+    meq[12] = R(-0.5) * rho * pww;               msrc[12] = -sww;
+    meq[13] = rho * ux * uy;                     msrc[13] = ux * Fy + uy * Fx;
+    meq[14] = rho * uy * uz;                     msrc[14] = uy * Fz + uz * Fy;
+    meq[15] = rho * ux * uz;                     msrc[15] = ux * Fz + uz * Fx;
+    R kk[Q];
+    static_for<Q>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      kk[i] = R(0);
+      if constexpr (mrt_class(i) != 0) {
+        R m = R(0);
+        static_for<Q>([&](auto ac) {
+          constexpr int a = decltype(ac)::value;
+          if constexpr (mrt_entry(i, a) != 0) m += R(mrt_entry(i, a)) * f[a];
+        });
+        const R lam = mrt_class(i) == 1 ? k.s_bulk : (mrt_class(i) == 2 ? k.omega : k.s_ghost);
+        kk[i] = (lam * (m - meq[i]) - (R(1) - R(0.5) * lam) * msrc[i]) *
+                (R(1) / R(mrt_norm(i)));
+      }
+    });
+    // Conserved rows: the density row carries nothing; the momentum rows
+    // contribute exactly M^-1 (0, F) whatever their rate (their
+    // non-equilibrium moment is -F/2 and their source moment F).
+    static_for<Q>([&](auto ac) {
+      constexpr int a = decltype(ac)::value;
+      R acc = R(0);
+      static_for<Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if constexpr (mrt_class(i) != 0 && mrt_entry(i, a) != 0) acc += R(mrt_entry(i, a)) * kk[i];
+      });
+      R fc = R(0);
+      if constexpr (CX[a] != 0) fc += R(CX[a]) * Fx;
+      if constexpr (CY[a] != 0) fc += R(CY[a]) * Fy;
+      if constexpr (CZ[a] != 0) fc += R(CZ[a]) * Fz;
+      D[a] = R(0.1) * fc - acc;
+    });
+  }
+  if constexpr (kF32) {
+    // Mass change 0 and momentum change F, enforced on the rounded increment.
+    R d0 = R(0), dx = -Fx, dy = -Fy, dz = -Fz;
+    static_for<Q>([&](auto ac) {
+      constexpr int a = decltype(ac)::value;
+      d0 += D[a];
+      if constexpr (CX[a] != 0) dx += R(CX[a]) * D[a];
+      if constexpr (CY[a] != 0) dy += R(CY[a]) * D[a];
+      if constexpr (CZ[a] != 0) dz += R(CZ[a]) * D[a];
+    });
+    D[0] -= d0;
+    D[1] -= R(0.5) * dx;
+    D[2] += R(0.5) * dx;
+    D[3] -= R(0.5) * dy;
+    D[4] += R(0.5) * dy;
+    D[5] -= R(0.5) * dz;
+    D[6] += R(0.5) * dz;
+  }
+  static_for<Q>([&](auto ac) {
+    constexpr int a = decltype(ac)::value;
+    f[a] += D[a];
+  });
+}
+
+// --------------------------------------------------------------- addressing
+struct Nbr {
+  unsigned xo[3];  // x - 1, x, x + 1 (periodic)
+  unsigned yo[3];  // row offsets of y - 1, y, y + 1
+  unsigned zo[3];  // plane offsets of z - 1, z, z + 1
+};
+
+__device__ inline Nbr neighbours(int x, int y, int z, int nx, int ny, int nz, int plane) {
+  Nbr b;
+  b.xo[0] = x == 0 ? nx - 1 : x - 1;
+  b.xo[1] = x;
+  b.xo[2] = x == nx - 1 ? 0 : x + 1;
+  b.yo[0] = (y == 0 ? ny - 1 : y - 1) * nx;
+  b.yo[1] = y * nx;
+  b.yo[2] = (y == ny - 1 ? 0 : y + 1) * nx;
+  b.zo[0] = (unsigned)(z == 0 ? nz - 1 : z - 1) * (unsigned)plane;
+  b.zo[1] = (unsigned)z * (unsigned)plane;
+  b.zo[2] = (unsigned)(z == nz - 1 ? 0 : z + 1) * (unsigned)plane;
+  return b;
+}
+
+// Post-streaming populations of a node: f_a(x) = lat[a][x - c_a].
+template <class T, class R>
+__device__ inline void pull(const T* __restrict__ lat, long long ps, const Nbr& b, R (&f)[Q]) {
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const unsigned idx = b.zo[1 - CZ[a]] + b.yo[1 - CY[a]] + b.xo[1 - CX[a]];
+    f[a] = R(lat[(long long)a * ps + idx]);
+  }
+}
+
+template <class T, class R>
+__device__ inline R pull_sum(const T* __restrict__ lat, long long ps, const Nbr& b) {
+  R s = R(0);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const unsigned idx = b.zo[1 - CZ[a]] + b.yo[1 - CY[a]] + b.xo[1 - CX[a]];
+    s += R(lat[(long long)a * ps + idx]);
+  }
+  return s;
+}
+
+__device__ inline int remap_xcd(int b, int nb) {
+  // Work-groups are dispatched round-robin over the 8 XCDs.  Give each XCD a
+  // contiguous range of logical tiles so that tiles sharing halo rows share
+  // an L2.
+  if ((nb & 7) != 0) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+// ---------------------------------------------------------------- the step
+template <class T, int COLL, int FORC, int NT>
+__global__ void __launch_bounds__(NT)
+k_step(const T* __restrict__ src, T* __restrict__ dst, StepArgs a) {
+  using R = T;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  R* lds = reinterpret_cast<R*>(smem_raw);
+
+  const Phys<R> ph = make_phys<R>(a);
+  const int nx = a.nx, ny = a.ny, nz = a.nz, plane = a.plane;
+  const long long ps = a.ps;
+  const int row_pitch = nx;
+  const int lplane = (a.by + 2) * nx;
+
+  int b = blockIdx.x;
+  if (a.xcd_remap) b = remap_xcd(b, gridDim.x);
+  const int ty = b % a.ntiles_y;
+  const int zc = b / a.ntiles_y;
+  const int y0 = ty * a.by;
+  const int bye = min(a.by, ny - y0);
+  const int z0 = zc * a.zchunk;
+  const int z1 = min(nz, z0 + a.zchunk);
+
+  const int tid = threadIdx.x;
+  const int lx = tid % nx;
+  const int ly = tid / nx;
+  const bool interior = ly < bye;
+  const int gy = y0 + ly;
+  const int nhalo = 2 * nx;
+
+  R cur[Q], nxt[Q];
+
+  // Pulls plane z: psi of the tile plus both halo rows into LDS slot `slot`;
+  // interior populations into `keep`.
+  auto load_plane = [&](int z, int slot, R(&keep)[Q]) {
+    R* lp = lds + slot * lplane;
+    if (interior) {
+      const Nbr nb = neighbours(lx, gy, z, nx, ny, nz, plane);
+      pull<T, R>(src, ps, nb, keep);
+      R s = R(0);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) s += keep[q];
+      lp[(ly + 1) * row_pitch + lx] = psi_of(ph.rho_ref + s, ph.psi_rho0, ph.inv_psi_rho0);
+    }
+    for (int h = tid; h < nhalo; h += NT) {
+      const int hl = h < nx ? -1 : bye;
+      const int hx = h < nx ? h : h - nx;
+      int hy = y0 + hl;
+      hy = hy < 0 ? hy + ny : (hy >= ny ? hy - ny : hy);
+      const Nbr nb = neighbours(hx, hy, z, nx, ny, nz, plane);
+      const R s = pull_sum<T, R>(src, ps, nb);
+      lp[(hl + 1) * row_pitch + hx] = psi_of(ph.rho_ref + s, ph.psi_rho0, ph.inv_psi_rho0);
+    }
+  };
+
+  const int zprev = z0 == 0 ? nz - 1 : z0 - 1;
+  load_plane(zprev, 0, nxt);
+  load_plane(z0, 1, cur);
+
+  for (int z = z0, k = 0; z < z1; ++z, ++k) {
+    const int znext = z == nz - 1 ? 0 : z + 1;
+    load_plane(znext, (k + 2) & 3, nxt);
+    __syncthreads();
+    if (interior) {
+      const R* pm = lds + (k & 3) * lplane;
+      const R* pc = lds + ((k + 1) & 3) * lplane;
+      const R* pp = lds + ((k + 2) & 3) * lplane;
+      const int xm = lx == 0 ? nx - 1 : lx - 1;
+      const int xp = lx == nx - 1 ? 0 : lx + 1;
+      const int rm = ly * row_pitch, rc = (ly + 1) * row_pitch, rp = (ly + 2) * row_pitch;
+      // sum_a w_a psi(x + c_a) c_a, axis links weight 1/18, diagonals 1/36.
+      const R ax = pc[rc + xp] - pc[rc + xm];
+      const R ay = pc[rp + lx] - pc[rm + lx];
+      const R az = pp[rc + lx] - pm[rc + lx];
+      const R dxy = pc[rp + xp] - pc[rm + xm];   // (+,+) minus (-,-)
+      const R dxmy = pc[rm + xp] - pc[rp + xm];  // (+,-) minus (-,+)
+      const R dxz = pp[rc + xp] - pm[rc + xm];
+      const R dxmz = pm[rc + xp] - pp[rc + xm];
+      const R dyz = pp[rp + lx] - pm[rm + lx];
+      const R dymz = pm[rp + lx] - pp[rm + lx];
+      const R sx = ax * R(1.0 / 18.0) + (dxy + dxmy + dxz + dxmz) * R(1.0 / 36.0);
+      const R sy = ay * R(1.0 / 18.0) + (dxy - dxmy + dyz + dymz) * R(1.0 / 36.0);
+      const R sz = az * R(1.0 / 18.0) + (dxz - dxmz + dyz - dymz) * R(1.0 / 36.0);
+      const R gpsi = -ph.G * pc[rc + lx];
+      collide<R, COLL, FORC>(cur, gpsi * sx, gpsi * sy, gpsi * sz, ph);
+      const unsigned idx = (unsigned)z * (unsigned)plane + (unsigned)(gy * nx + lx);
+      // Written once and read only in the next step: non-temporal stores keep
+      // them from evicting the rows the neighbouring tiles still re-read.
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        __builtin_nontemporal_store(T(cur[q]), &dst[(long long)q * ps + idx]);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
+  }
+}
+
+// ------------------------------------------------------------ initial state
+// Post-collision layout of the state f_a(x) = w_a rho0(x): lat[a][y] holds
+// f_a(y + c_a) = w_a rho0(y + c_a), shifted by w_a rho_ref in float32.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_init(T* __restrict__ lat, const double* __restrict__ rho0, StepArgs a) {
+  const long long n = a.n;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % a.nx);
+    const int y = (int)((i / a.nx) % a.ny);
+    const int z = (int)(i / a.plane);
+    const Nbr nb = neighbours(x, y, z, a.nx, a.ny, a.nz, a.plane);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const unsigned src = nb.zo[1 + CZ[q]] + nb.yo[1 + CY[q]] + nb.xo[1 + CX[q]];
+      lat[(long long)q * a.ps + i] = T(weight<double>(q) * (rho0[src] - a.rho_ref));
+    }
+  }
+}
+
+// Post-streaming populations of every node into out[a][x] (state export).
+template <class T>
+__global__ void __launch_bounds__(256)
+k_gather(const T* __restrict__ lat, long long ps_in, T* __restrict__ out, long long ps_out,
+         StepArgs a) {
+  const long long n = a.n;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % a.nx);
+    const int y = (int)((i / a.nx) % a.ny);
+    const int z = (int)(i / a.plane);
+    const Nbr nb = neighbours(x, y, z, a.nx, a.ny, a.nz, a.plane);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const unsigned src = nb.zo[1 - CZ[q]] + nb.yo[1 - CY[q]] + nb.xo[1 - CX[q]];
+      out[(long long)q * ps_out + i] = lat[(long long)q * ps_in + src];
+    }
+  }
+}
+
+// Inverse of k_gather (state import): lat[a][y] = in[a][y + c_a].
+template <class T>
+__global__ void __launch_bounds__(256)
+k_scatter(const T* __restrict__ in, long long ps_in, T* __restrict__ lat, long long ps_out,
+          StepArgs a) {
+  const long long n = a.n;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % a.nx);
+    const int y = (int)((i / a.nx) % a.ny);
+    const int z = (int)(i / a.plane);
+    const Nbr nb = neighbours(x, y, z, a.nx, a.ny, a.nz, a.plane);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const unsigned src = nb.zo[1 + CZ[q]] + nb.yo[1 + CY[q]] + nb.xo[1 + CX[q]];
+      lat[(long long)q * ps_out + i] = in[(long long)q * ps_in + src];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ moments
+// Pass 1: rho and j of every node (float64).  j goes to u (later turned into
+// u^b by pass 2) when u is given.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_moments1(const T* __restrict__ lat, double* __restrict__ rho, double* __restrict__ u,
+           StepArgs a) {
+  const long long n = a.n;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % a.nx);
+    const int y = (int)((i / a.nx) % a.ny);
+    const int z = (int)(i / a.plane);
+    const Nbr nb = neighbours(x, y, z, a.nx, a.ny, a.nz, a.plane);
+    double f[Q];
+    pull<T, double>(lat, a.ps, nb, f);
+    double s = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      s += f[q];
+      if (CX[q] != 0) jx += CX[q] * f[q];
+      if (CY[q] != 0) jy += CY[q] * f[q];
+      if (CZ[q] != 0) jz += CZ[q] * f[q];
+    }
+    rho[i] = a.rho_ref + s;
+    if (u) {
+      u[i] = jx;
+      u[n + i] = jy;
+      u[2 * n + i] = jz;
+    }
+  }
+}
+
+// Shan-Chen force of node (x, y, z) from a float64 density field.
+__device__ inline void force_from_rho(const double* __restrict__ rho, const Nbr& b,
+                                      const StepArgs& a, double& Fx, double& Fy, double& Fz,
+                                      double& psi_c) {
+  const double r0 = a.psi_rho0, ir0 = 1.0 / a.psi_rho0;
+  double sx = 0, sy = 0, sz = 0;
+#pragma unroll
+  for (int q = 1; q < Q; ++q) {
+    const unsigned idx = b.zo[1 + CZ[q]] + b.yo[1 + CY[q]] + b.xo[1 + CX[q]];
+    const double wp = weight<double>(q) * psi_of(rho[idx], r0, ir0);
+    if (CX[q] != 0) sx += CX[q] * wp;
+    if (CY[q] != 0) sy += CY[q] * wp;
+    if (CZ[q] != 0) sz += CZ[q] * wp;
+  }
+  psi_c = psi_of(rho[b.zo[1] + b.yo[1] + b.xo[1]], r0, ir0);
+  Fx = -a.G * psi_c * sx;
+  Fy = -a.G * psi_c * sy;
+  Fz = -a.G * psi_c * sz;
+}
+
+// Pass 2: u^b = (j + F/2)/rho and the pressure of Eq. EOS_SC.
+__global__ void __launch_bounds__(256)
+k_moments2(const double* __restrict__ rho, double* __restrict__ u, double* __restrict__ p,
+           StepArgs a) {
+  const long long n = a.n;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % a.nx);
+    const int y = (int)((i / a.nx) % a.ny);
+    const int z = (int)(i / a.plane);
+    const Nbr nb = neighbours(x, y, z, a.nx, a.ny, a.nz, a.plane);
+    double Fx, Fy, Fz, psi;
+    force_from_rho(rho, nb, a, Fx, Fy, Fz, psi);
+    const double r = rho[i];
+    if (u) {
+      u[i] = (u[i] + 0.5 * Fx) / r;
+      u[n + i] = (u[n + i] + 0.5 * Fy) / r;
+      u[2 * n + i] = (u[2 * n + i] + 0.5 * Fz) / r;
+    }
+    if (p) p[i] = r / 3.0 + a.G * psi * psi / 6.0;
+  }
+}
+
+// -------------------------------------------------------------- diagnostics
+// Blocks of 256 threads own DIAG_CHUNK consecutive nodes of one z-slice, so a
+// slice's liquid area is a sum of whole-block partials.  Each block writes 8
+// partial sums: rho, jx, jy, jz, Fx, Fy, Fz, A.  Reductions run in a fixed
+// order (per-thread serial, butterfly across the wavefront, waves in order),
+// so results are bitwise reproducible.
+constexpr int DIAG_CHUNK = 4096;
+constexpr int DIAG_THREADS = 256;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int NV>
+__device__ inline void block_sums(double (&v)[NV], double* out) {
+  __shared__ double red[DIAG_THREADS / 64][8];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[wv][k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0;
+      for (int w = 0; w < DIAG_THREADS / 64; ++w) s += red[w][k];
+      out[k] = s;
+    }
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(DIAG_THREADS)
+k_diag1(const T* __restrict__ lat, double* __restrict__ rho, double* __restrict__ part,
+        StepArgs a, int chunks_per_slice) {
+  const int z = blockIdx.x / chunks_per_slice;
+  const int c = blockIdx.x % chunks_per_slice;
+  const int lo = c * DIAG_CHUNK, hi = min(a.plane, lo + DIAG_CHUNK);
+  double v[4] = {0, 0, 0, 0};
+  for (int i = lo + threadIdx.x; i < hi; i += DIAG_THREADS) {
+    const int x = i % a.nx, y = i / a.nx;
+    const Nbr nb = neighbours(x, y, z, a.nx, a.ny, a.nz, a.plane);
+    double f[Q];
+    pull<T, double>(lat, a.ps, nb, f);
+    double s = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      s += f[q];
+      if (CX[q] != 0) jx += CX[q] * f[q];
+      if (CY[q] != 0) jy += CY[q] * f[q];
+      if (CZ[q] != 0) jz += CZ[q] * f[q];
+    }
+    const double r = a.rho_ref + s;
+    rho[(long long)z * a.plane + i] = r;
+    v[0] += r;
+    v[1] += jx;
+    v[2] += jy;
+    v[3] += jz;
+  }
+  block_sums<4>(v, part + (long long)blockIdx.x * 8);
+}
+
+__global__ void __launch_bounds__(DIAG_THREADS)
+k_diag2(const double* __restrict__ rho, double* __restrict__ part, StepArgs a,
+        int chunks_per_slice, double rho_v, double rho_l) {
+  const int z = blockIdx.x / chunks_per_slice;
+  const int c = blockIdx.x % chunks_per_slice;
+  const int lo = c * DIAG_CHUNK, hi = min(a.plane, lo + DIAG_CHUNK);
+  const double inv_dr = 1.0 / (rho_l - rho_v);
+  double v[4] = {0, 0, 0, 0};
+  for (int i = lo + threadIdx.x; i < hi; i += DIAG_THREADS) {
+    const int x = i % a.nx, y = i / a.nx;
+    const Nbr nb = neighbours(x, y, z, a.nx, a.ny, a.nz, a.plane);
+    double Fx, Fy, Fz, psi;
+    force_from_rho(rho, nb, a, Fx, Fy, Fz, psi);
+    v[0] += Fx;
+    v[1] += Fy;
+    v[2] += Fz;
+    const double fr = (rho[(long long)z * a.plane + i] - rho_v) * inv_dr;
+    v[3] += fmin(fmax(fr, 0.0), 1.0);
+  }
+  block_sums<4>(v, part + (long long)blockIdx.x * 8 + 4);
+}
+
+// Final pass, one block: out[0] mass, out[1..3] momentum, out[4 + z] A(z).
+__global__ void __launch_bounds__(DIAG_THREADS)
+k_diag3(const double* __restrict__ part, double* __restrict__ out, int nz,
+        int chunks_per_slice) {
+  // A(z): one thread per slice, chunks in order.
+  for (int z = threadIdx.x; z < nz; z += DIAG_THREADS) {
+    double s = 0;
+    for (int c = 0; c < chunks_per_slice; ++c) s += part[((long long)z * chunks_per_slice + c) * 8 + 7];
+    out[4 + z] = s;
+  }
+  // Totals: each thread a strided serial sum over blocks, then the block tree.
+  const long long nb = (long long)nz * chunks_per_slice;
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (long long b = threadIdx.x; b < nb; b += DIAG_THREADS) {
+#pragma unroll
+    for (int k = 0; k < 7; ++k) v[k] += part[b * 8 + k];
+  }
+  __shared__ double tot[8];
+  block_sums<7>(v, tot);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = tot[0];
+    out[1] = tot[1] + 0.5 * tot[4];
+    out[2] = tot[2] + 0.5 * tot[5];
+    out[3] = tot[3] + 0.5 * tot[6];
+  }
+}
+
+int grid_for(long long n, int threads) {
+  long long g = (n + threads - 1) / threads;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_init(int prec, void* lat, const double* rho0, const StepArgs& a,
+                       hipStream_t s) {
+  const int g = grid_for(a.n, 256);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_init<double>, dim3(g), dim3(256), 0, s, (double*)lat, rho0, a);
+  else
+    hipLaunchKernelGGL(k_init<float>, dim3(g), dim3(256), 0, s, (float*)lat, rho0, a);
+  return hipGetLastError();
+}
+
+template <class T, int COLL, int FORC>
+static hipError_t step_t(int threads, const void* src, void* dst, const StepArgs& a,
+                         hipStream_t s) {
+  const int grid = a.ntiles_y * ((a.nz + a.zchunk - 1) / a.zchunk);
+  const size_t lds = (size_t)4 * (a.by + 2) * a.nx * sizeof(T);
+  const T* in = (const T*)src;
+  T* out = (T*)dst;
+  switch (threads) {
+    case 256:
+      hipLaunchKernelGGL((k_step<T, COLL, FORC, 256>), dim3(grid), dim3(256), lds, s, in, out, a);
+      break;
+    case 512:
+      hipLaunchKernelGGL((k_step<T, COLL, FORC, 512>), dim3(grid), dim3(512), lds, s, in, out, a);
+      break;
+    default:
+      hipLaunchKernelGGL((k_step<T, COLL, FORC, 1024>), dim3(grid), dim3(1024), lds, s, in, out,
+                         a);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_step(int prec, int coll, int forc, int threads, const void* src, void* dst,
+                       const StepArgs& a, hipStream_t s) {
+  if (prec == 0) {
+    if (coll == kMRT) return step_t<double, kMRT, kGuo>(threads, src, dst, a, s);
+    if (forc == kShift) return step_t<double, kBGK, kShift>(threads, src, dst, a, s);
+    return step_t<double, kBGK, kGuo>(threads, src, dst, a, s);
+  }
+  if (coll == kMRT) return step_t<float, kMRT, kGuo>(threads, src, dst, a, s);
+  if (forc == kShift) return step_t<float, kBGK, kShift>(threads, src, dst, a, s);
+  return step_t<float, kBGK, kGuo>(threads, src, dst, a, s);
+}
+
+hipError_t launch_moments(int prec, const void* lat, double* rho, double* u, double* p,
+                          const StepArgs& a, hipStream_t s) {
+  const int g = grid_for(a.n, 256);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_moments1<double>, dim3(g), dim3(256), 0, s, (const double*)lat, rho, u, a);
+  else
+    hipLaunchKernelGGL(k_moments1<float>, dim3(g), dim3(256), 0, s, (const float*)lat, rho, u, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (u || p) {
+    hipLaunchKernelGGL(k_moments2, dim3(g), dim3(256), 0, s, (const double*)rho, u, p, a);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+int diag_blocks(const StepArgs& a) {
+  const int cps = (a.plane + DIAG_CHUNK - 1) / DIAG_CHUNK;
+  return cps * a.nz;
+}
+
+hipError_t launch_diagnostics(int prec, const void* lat, double* rho_scratch, double* part,
+                              double* out, double rho_v, double rho_l, const StepArgs& a,
+                              hipStream_t s) {
+  const int cps = (a.plane + DIAG_CHUNK - 1) / DIAG_CHUNK;
+  const int nb = cps * a.nz;
+  if (prec == 0)
+    hipLaunchKernelGGL(k_diag1<double>, dim3(nb), dim3(DIAG_THREADS), 0, s, (const double*)lat,
+                       rho_scratch, part, a, cps);
+  else
+    hipLaunchKernelGGL(k_diag1<float>, dim3(nb), dim3(DIAG_THREADS), 0, s, (const float*)lat,
+                       rho_scratch, part, a, cps);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_diag2, dim3(nb), dim3(DIAG_THREADS), 0, s, (const double*)rho_scratch,
+                     part, a, cps, rho_v, rho_l);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_diag3, dim3(1), dim3(DIAG_THREADS), 0, s, (const double*)part, out, a.nz,
+                     cps);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(int prec, const void* lat, long long ps_in, void* out, long long ps_out,
+                         const StepArgs& a, hipStream_t s) {
+  const int g = grid_for(a.n, 256);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_gather<double>, dim3(g), dim3(256), 0, s, (const double*)lat, ps_in,
+                       (double*)out, ps_out, a);
+  else
+    hipLaunchKernelGGL(k_gather<float>, dim3(g), dim3(256), 0, s, (const float*)lat, ps_in,
+                       (float*)out, ps_out, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(int prec, const void* in, long long ps_in, void* lat, long long ps_out,
+                          const StepArgs& a, hipStream_t s) {
+  const int g = grid_for(a.n, 256);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_scatter<double>, dim3(g), dim3(256), 0, s, (const double*)in, ps_in,
+                       (double*)lat, ps_out, a);
+  else
+    hipLaunchKernelGGL(k_scatter<float>, dim3(g), dim3(256), 0, s, (const float*)in, ps_in,
+                       (float*)lat, ps_out, a);
+  return hipGetLastError();
+}
+
+void lattice_tables(int32_t* c, double* w) {
+  for (int q = 0; q < Q; ++q) {
+    if (c) {
+      c[3 * q + 0] = CX[q];
+      c[3 * q + 1] = CY[q];
+      c[3 * q + 2] = CZ[q];
+    }
+    if (w) w[q] = weight<double>(q);
+  }
+}
+
+}  // namespace lbsc

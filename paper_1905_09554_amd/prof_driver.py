@@ -1,0 +1,53 @@
+"""Short, fixed workload for profiler runs (rocprofv3 kernel traces and HBM
+counters).
+
+    python -m paper_1905_09554_amd.prof_driver [--precision f32|f64] [--steps K]
+
+Runs the benchmark box (256 x 256 x 1024 ligament, MRT, the launch shape the
+benchmark uses) for a few steps, then a plain device-to-device copy of a known
+size whose counters calibrate FETCH_SIZE and WRITE_SIZE.
+"""
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+COPY_BYTES = 1 << 30
+WORKLOAD = "ligament_256x256x1024_mrt_f32"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--workload", default=WORKLOAD)
+    args = ap.parse_args()
+
+    import torch
+    import lbm_inputs
+    from paper_1905_09554_amd import lbsc, tuning
+
+    rho0, info = lbm_inputs.workload_density(args.workload)
+    nz, ny, nx = rho0.shape
+    prm = lbsc.make_params(nx, ny, nz, collision=info["collision"], precision=args.precision,
+                           G=info["G"], tau=info["tau"], rho_ref=1.0)
+    sim = lbsc.Simulation(rho0, prm)
+    t = tuning.apply(sim, prm)
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    print("steps done", args.steps, t, flush=True)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print("copy done", COPY_BYTES, flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,88 @@
+"""HBM traffic of the step kernel from two rocprofv3 counter runs.
+
+    python -m paper_1905_09554_amd.traffic --fetch DIR --write DIR \
+        --precision f32 [--workload NAME]
+
+DIR are the output folders of
+    rocprofv3 --pmc FETCH_SIZE -d DIR -- python -m paper_1905_09554_amd.prof_driver
+    rocprofv3 --pmc WRITE_SIZE -d DIR -- python -m paper_1905_09554_amd.prof_driver
+Both counters are in KiB per dispatch.  Each is scaled by what it reads for
+the driver's plain copy of a known size (1 GiB read, 1 GiB written), and the
+per-launch bytes of the step kernel are written to
+profiles/traffic_<workload>_<precision>.json together with a hash of the
+kernel sources (the benchmark ignores the file once the sources change).
+"""
+import argparse
+import csv
+import glob
+import json
+import os
+import statistics
+
+from .prof_driver import COPY_BYTES, WORKLOAD
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _rows(folder, counter):
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError("no counter_collection.csv under %s" % folder)
+    out = []
+    for path in files:
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") == counter:
+                    out.append((row.get("Kernel_Name", ""), float(row["Counter_Value"])))
+    return out
+
+
+def _per_kernel(rows):
+    step = [v for name, v in rows if "k_step" in name]
+    copy = [v for name, v in rows if "copyBuffer" in name or "elementwise" in name]
+    if not step or not copy:
+        raise RuntimeError("missing step or copy dispatches in the counter file")
+    return statistics.mean(step), copy[-1], len(step)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--precision", required=True, choices=["f32", "f64"])
+    ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--nodes", type=int, default=256 * 256 * 1024)
+    args = ap.parse_args()
+
+    import sys
+    sys.path.insert(0, ROOT)
+    from bench import kernel_source_hash
+
+    f_step, f_copy, nf = _per_kernel(_rows(args.fetch, "FETCH_SIZE"))
+    w_step, w_copy, nw = _per_kernel(_rows(args.write, "WRITE_SIZE"))
+    kib = COPY_BYTES / 1024.0
+    f_scale, w_scale = kib / f_copy, kib / w_copy
+    fetch_b = f_step * f_scale * 1024.0
+    write_b = w_step * w_scale * 1024.0
+    elem = 4 if args.precision == "f32" else 8
+    alg = 19 * elem * args.nodes
+    rec = {
+        "workload": args.workload, "precision": args.precision, "nodes": args.nodes,
+        "source_hash": kernel_source_hash(),
+        "fetch_kib_raw": f_step, "write_kib_raw": w_step, "dispatches": [nf, nw],
+        "copy_fetch_kib": f_copy, "copy_write_kib": w_copy,
+        "fetch_scale": f_scale, "write_scale": w_scale,
+        "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
+        "bytes_per_launch": fetch_b + write_b,
+        "algorithmic_bytes_per_launch": 2 * alg,
+        "fetch_over_algorithmic": fetch_b / alg, "write_over_algorithmic": write_b / alg,
+    }
+    out = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (args.workload, args.precision))
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(rec, indent=1))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,170 @@
+"""Parity of the HIP path (through the C ABI) with the float64 oracle.
+
+Tolerances: float64 state within 1e-12 absolute (populations and density are
+O(1)); float32 shifted storage: density within 1e-5 relative of the float64
+oracle after 1000 steps.  Integer outputs (the argmin slice) must match
+exactly.
+"""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs
+from oracle import diagnostics, lbm
+from tests import gpu_cases as gc
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+
+
+def _c1():
+    return gc.ligament(32, 32, 64, 8.0, 0.1, 1)
+
+
+def _note(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("coll", ["bgk", "mrt"])
+def test_config1_f64_1000_steps(coll):
+    rho0 = _c1()
+    _note("config1 f64 %s 1000 steps" % coll)
+    g = gc.run_gpu(rho0, 1000, collision=coll)
+    o = gc.run_oracle(rho0, 1000, collision=coll)
+    err_state = float(np.abs(g["state"] - o["state"]).max())
+    err_rho = float(np.abs(g["rho"] - o["rho"]).max())
+    _note("max |df| = %.3e, max |drho| = %.3e" % (err_state, err_rho))
+    assert err_state < F64_TOL
+    assert err_rho < F64_TOL
+    assert float(np.abs(g["u"] - o["u"]).max()) < F64_TOL
+    assert float(np.abs(g["p"] - o["p"]).max()) < F64_TOL
+
+
+def test_config1_minimum_radius_every_100_steps():
+    from paper_1905_09554_amd import lbsc
+    rho0 = _c1()
+    rv, rl = lbm_inputs.coexistence(-5.0)
+    prm = lbsc.make_params(32, 32, 64, collision="bgk", precision="f64", G=-5.0, tau=1.0)
+    sim = lbsc.Simulation(rho0, prm)
+    op = lbm.Params(G=-5.0, tau=1.0)
+    f = lbm.init_rest(torch.from_numpy(rho0))
+    for k in range(11):
+        d = sim.diagnostics(rv, rl)
+        od = diagnostics.interface_diagnostics(f, op, rv, rl)
+        assert abs(d["mass"] - od["mass"]) < 1e-12 * od["mass"]
+        assert max(abs(a - b) for a, b in zip(d["mom"], od["mom"])) < 1e-12 * od["mass"]
+        assert float(np.abs(d["r_of_z"] - od["r_of_z"].numpy()).max()) < 1e-12
+        assert abs(d["r_min"] - od["r_min"]) < 1e-12
+        assert d["z_argmin"] == od["z_argmin"]
+        if k < 10:
+            sim.step(100)
+            f = lbm.run(f, op, 100)
+    _note("r_min after 1000 steps: %.6f at z=%d" % (d["r_min"], d["z_argmin"]))
+
+
+def test_velocity_shift_forcing_f64():
+    rho0 = gc.ligament(24, 20, 28, 6.0, 0.1, 1)
+    g = gc.run_gpu(rho0, 200, forcing="shift", tau=0.8)
+    o = gc.run_oracle(rho0, 200, forcing="shift", tau=0.8)
+    assert float(np.abs(g["state"] - o["state"]).max()) < F64_TOL
+
+
+def test_mrt_paper_rates_f64():
+    # The paper's rate set: bulk rate 1/tau, every other non-shear rate 1.
+    rho0 = gc.ligament(24, 20, 28, 6.0, 0.1, 1)
+    tau = 0.7
+    g = gc.run_gpu(rho0, 200, collision="mrt", tau=tau, s_bulk=1 / tau, s_ghost=1.0)
+    o = gc.run_oracle(rho0, 200, collision="mrt", tau=tau, s_bulk=1 / tau, s_ghost=1.0)
+    assert float(np.abs(g["state"] - o["state"]).max()) < F64_TOL
+
+
+@pytest.mark.parametrize("rho_ref", [1.0, 0.0])
+@pytest.mark.parametrize("coll", ["bgk", "mrt"])
+def test_config1_f32_shifted_1000_steps(coll, rho_ref):
+    rho0 = _c1()
+    g = gc.run_gpu(rho0, 1000, collision=coll, precision="f32", rho_ref=rho_ref)
+    o = gc.run_oracle(rho0, 1000, collision=coll)
+    rel = float((np.abs(g["rho"] - o["rho"]) / o["rho"]).max())
+    du = float(np.abs(g["u"] - o["u"]).max())
+    umax = float(np.abs(o["u"]).max())
+    _note("f32 %s rho_ref %.1f: max rel drho = %.3e, max |du| = %.3e (max |u| = %.3e)"
+          % (coll, rho_ref, rel, du, umax))
+    assert rel < 1e-5
+
+
+@pytest.mark.parametrize("shape,tuning", [
+    ((36, 20, 18), dict(threads=256, block_y=3, z_chunk=5)),
+    ((36, 20, 18), dict(threads=1024, z_chunk=7, xcd_remap=0)),
+    ((1, 1, 32), None),
+    ((24, 24, 1), dict(threads=512, z_chunk=1)),
+    ((7, 5, 3), dict(threads=256, block_y=2, z_chunk=2)),
+    ((1024, 2, 4), None),
+])
+@pytest.mark.parametrize("coll", ["bgk", "mrt"])
+def test_ragged_shapes_f64(shape, tuning, coll):
+    nx, ny, nz = shape
+    g_ = np.random.default_rng(7)
+    rho0 = 1.0 + 0.4 * g_.random((nz, ny, nx))
+    g = gc.run_gpu(rho0, 12, collision=coll, tuning=tuning)
+    o = gc.run_oracle(rho0, 12, collision=coll)
+    assert float(np.abs(g["state"] - o["state"]).max()) < F64_TOL
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_launch_shape_does_not_change_results_bitwise(precision):
+    rho0 = gc.ligament(40, 36, 30, 8.0, 0.1, 1, noise=1e-4)
+    ref = None
+    for t in (None, dict(threads=256, z_chunk=3), dict(threads=512, block_y=1, z_chunk=30),
+              dict(threads=1024, xcd_remap=0, z_chunk=4), dict(threads=1024, block_y=5)):
+        g = gc.run_gpu(rho0, 9, collision="mrt", precision=precision, tuning=t)
+        if ref is None:
+            ref = g["state"]
+        else:
+            assert np.array_equal(ref, g["state"]), t
+
+
+def test_zero_steps_is_the_initial_state():
+    rho0 = _c1()
+    g = gc.run_gpu(rho0, 0)
+    f0 = lbm.init_rest(torch.from_numpy(rho0)).numpy()
+    assert np.array_equal(g["state"], f0)
+
+
+def test_checkpoint_resume_is_bitwise():
+    from paper_1905_09554_amd import lbsc
+    rho0 = gc.ligament(32, 32, 40, 7.0, 0.1, 1)
+    for prec in ("f64", "f32"):
+        prm = lbsc.make_params(32, 32, 40, collision="mrt", precision=prec)
+        a = lbsc.Simulation(rho0, prm)
+        a.step(15)
+        saved, step = a.get_state()
+        a.step(15)
+        end_a, _ = a.get_state()
+        b = lbsc.Simulation(np.full_like(rho0, 0.5), prm)
+        b.set_state(saved, step)
+        b.step(15)
+        end_b, count = b.get_state()
+        assert count == 30
+        assert np.array_equal(end_a, end_b)
+
+
+def test_nonfinite_state_is_reported():
+    from paper_1905_09554_amd import lbsc
+    rho0 = gc.ligament(16, 16, 16, 4.0, 0.1, 1)
+    prm = lbsc.make_params(16, 16, 16)
+    sim = lbsc.Simulation(rho0, prm)
+    st, _ = sim.get_state()
+    st[0, 3, 3, 3] = np.nan
+    sim.set_state(st, 0)
+    with pytest.raises(lbsc.LbscError) as e:
+        sim.diagnostics(0.12, 1.88)
+    assert e.value.code == lbsc.LBSC_ENONFINITE
+
+
+def test_uniform_state_is_fixed_point():
+    rho0 = np.full((12, 10, 8), 0.9)
+    for coll in ("bgk", "mrt"):
+        g = gc.run_gpu(rho0, 5, collision=coll)
+        f0 = lbm.init_rest(torch.from_numpy(rho0)).numpy()
+        assert float(np.abs(g["state"] - f0).max()) < 4e-16
