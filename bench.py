@@ -113,7 +113,7 @@ def run_gpu(rho0, info, precision, steps, warmup):
     }
 
 
-def cpu_baseline(rho0, info, nz_sample=16, steps=12):
+def cpu_baseline(rho0, info, nz_sample=16, steps=40):
     """The float64 oracle on the host: the first nz_sample planes of the same
     input as a periodic slab, `steps` steps, reported in MLUPS."""
     import torch

@@ -84,14 +84,15 @@ typedef struct lbsc_diag {
 } lbsc_diag;
 
 /* Kernel launch shape and population layout; the autotuner picks these.
- * threads, z_chunk, block_y: 0 means the default; pop_pad < 0 means the
- * default.  Changing pop_pad re-lays the state out in place (same values). */
+ * threads, z_chunk, block_y, nodes_per_thread: 0 means the default; pop_pad
+ * < 0 means the default.  Changing pop_pad re-lays the state out in place (same values). */
 typedef struct lbsc_tuning {
   int32_t threads;     /* work-group size of the fused step: 256, 512, 1024   */
   int32_t z_chunk;     /* planes marched per work-group (>= 1)                */
   int32_t xcd_remap;   /* 1: map neighbouring tiles onto one XCD (L2), 0: off */
   int32_t block_y;     /* rows per tile; 0 = as many as the work-group holds  */
   int32_t pop_pad;     /* extra elements between population arrays, <= 65536 */
+  int32_t nodes_per_thread; /* interior nodes each thread carries: 1 or 2      */
 } lbsc_tuning;
 
 /* Bytes of device memory a context with these parameters needs: two

@@ -13,6 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbsc.so")
+PROBE = os.path.join(PKG, "hbm_probe")
 SOURCES = ["lbsc_device.hip", "lbsc_api.hip"]
 ARCH = "gfx950"
 
@@ -51,6 +52,13 @@ def build(verbose=False):
     os.replace(tmp, LIB)
     for o in objs:
         os.remove(o)
+    # Bandwidth calibration program (streaming kernels of known traffic).
+    cmd = [hipcc(), os.path.join(CSRC, "hbm_probe.hip"), "-o", PROBE + ".tmp"] + [
+        f for f in HIPCC_FLAGS if f not in ("-fPIC",)]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(PROBE + ".tmp", PROBE)
     return LIB
 
 

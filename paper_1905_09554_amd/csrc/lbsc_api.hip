@@ -89,10 +89,13 @@ lbsc::StepArgs make_args(const lbsc_params& p, const lbsc_tuning& t) {
   a.plane = p.nx * p.ny;
   a.n = (long long)p.nx * p.ny * p.nz;
   a.ps = (a.n + 63) / 64 * 64 + (t.pop_pad >= 0 ? t.pop_pad : kDefaultPad);
-  int by = t.block_y > 0 ? t.block_y : t.threads / p.nx;
-  if (by > t.threads / p.nx) by = t.threads / p.nx;
+  const int rows = t.nodes_per_thread * t.threads / p.nx;  // rows the group can hold
+  int by = t.block_y > 0 ? t.block_y : rows;
+  if (by > rows) by = rows;
   if (by < 1) by = 1;
   if (by > p.ny) by = p.ny;
+  // Four psi planes of (by + 2) rows must fit the 160 KB of LDS of a CU.
+  while (by > 1 && 4LL * (by + 2) * p.nx * (long long)elem_size(p) > 160 * 1024) --by;
   a.by = by;
   a.ntiles_y = (p.ny + by - 1) / by;
   a.zchunk = t.z_chunk > 0 ? (t.z_chunk > p.nz ? p.nz : t.z_chunk) : p.nz;
@@ -116,9 +119,10 @@ lbsc_tuning default_tuning(const lbsc_params& p) {
   t.block_y = 0;
   t.xcd_remap = 1;
   t.pop_pad = -1;
+  t.nodes_per_thread = 1;
   // Enough work-groups to fill 256 CUs a few times over, but long z-marches
   // so the two extra halo planes of each chunk stay a small fraction.
-  const int by = std::max(1, std::min(p.ny, t.threads / p.nx));
+  const int by = std::max(1, std::min(p.ny, t.nodes_per_thread * t.threads / p.nx));
   const long long tiles = (p.ny + by - 1) / by;
   long long zc = (tiles * p.nz + 2047) / 2048;
   if (zc < 8) zc = 8;
@@ -226,8 +230,8 @@ int lbsc_step(lbsc_ctx* c, int64_t nsteps) {
   if (nsteps < 0) return fail(&c->err, LBSC_EINVAL, "nsteps must be >= 0");
   for (int64_t i = 0; i < nsteps; ++i) {
     hipError_t e = lbsc::launch_step(c->p.precision, c->p.collision, c->p.forcing,
-                                     c->tune.threads, c->lat[c->cur], c->lat[c->cur ^ 1], c->a,
-                                     c->stream);
+                                     c->tune.threads, c->tune.nodes_per_thread, c->lat[c->cur],
+                                     c->lat[c->cur ^ 1], c->a, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "step launch");
     c->cur ^= 1;
     c->step += 1;
@@ -328,8 +332,11 @@ int lbsc_set_tuning(lbsc_ctx* c, const lbsc_tuning* t) {
     n.threads = t->threads;
   }
   if (t->z_chunk < 0 || t->block_y < 0) return fail(&c->err, LBSC_EINVAL, "negative tuning value");
-  if (t->block_y && (long long)t->block_y * c->p.nx > n.threads)
-    return fail(&c->err, LBSC_EINVAL, "block_y * nx exceeds the work-group size");
+  if (t->nodes_per_thread < 0 || t->nodes_per_thread > 2)
+    return fail(&c->err, LBSC_EINVAL, "nodes_per_thread must be 0, 1 or 2");
+  if (t->nodes_per_thread) n.nodes_per_thread = t->nodes_per_thread;
+  if (t->block_y && (long long)t->block_y * c->p.nx > (long long)n.nodes_per_thread * n.threads)
+    return fail(&c->err, LBSC_EINVAL, "block_y * nx exceeds nodes_per_thread * threads");
   if (t->pop_pad > kMaxPad) return fail(&c->err, LBSC_EINVAL, "pop_pad exceeds 65536");
   if (t->z_chunk) n.z_chunk = t->z_chunk;
   n.block_y = t->block_y;

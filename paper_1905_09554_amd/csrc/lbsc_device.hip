@@ -336,7 +336,14 @@ __device__ inline int remap_xcd(int b, int nb) {
 }
 
 // ---------------------------------------------------------------- the step
-template <class T, int COLL, int FORC, int NT>
+// One work-group of NT threads owns rows [y0, y0 + by) (by <= K NT / nx) of
+// all x and planes [z0, z1); each thread carries K interior nodes (tile
+// indices tid + k NT).  Iteration of plane z: pull plane z+1 (tile and both
+// halo rows), publish psi(z+1) to LDS slot (k+2)%4, barrier, then force and
+// collision of plane z from the populations kept in registers since the
+// previous iteration.  Four psi slots make one barrier per iteration enough:
+// the slot written at iteration k+1 was last read at iteration k-1.
+template <class T, int COLL, int FORC, int NT, int K>
 __global__ void __launch_bounds__(NT)
 k_step(const T* __restrict__ src, T* __restrict__ dst, StepArgs a) {
   using R = T;
@@ -346,7 +353,6 @@ k_step(const T* __restrict__ src, T* __restrict__ dst, StepArgs a) {
   const Phys<R> ph = make_phys<R>(a);
   const int nx = a.nx, ny = a.ny, nz = a.nz, plane = a.plane;
   const long long ps = a.ps;
-  const int row_pitch = nx;
   const int lplane = (a.by + 2) * nx;
 
   int b = blockIdx.x;
@@ -359,25 +365,38 @@ k_step(const T* __restrict__ src, T* __restrict__ dst, StepArgs a) {
   const int z1 = min(nz, z0 + a.zchunk);
 
   const int tid = threadIdx.x;
-  const int lx = tid % nx;
-  const int ly = tid / nx;
-  const bool interior = ly < bye;
-  const int gy = y0 + ly;
+  int lx[K], ly[K];
+  bool interior[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * NT;
+    lx[k] = i % nx;
+    ly[k] = i / nx;
+    interior[k] = ly[k] < bye;
+  }
   const int nhalo = 2 * nx;
 
-  R cur[Q], nxt[Q];
+  R cur[K][Q], nxt[K][Q];
 
   // Pulls plane z: psi of the tile plus both halo rows into LDS slot `slot`;
   // interior populations into `keep`.
-  auto load_plane = [&](int z, int slot, R(&keep)[Q]) {
+  auto load_plane = [&](int z, int slot, R(&keep)[K][Q]) {
     R* lp = lds + slot * lplane;
-    if (interior) {
-      const Nbr nb = neighbours(lx, gy, z, nx, ny, nz, plane);
-      pull<T, R>(src, ps, nb, keep);
-      R s = R(0);
 #pragma unroll
-      for (int q = 0; q < Q; ++q) s += keep[q];
-      lp[(ly + 1) * row_pitch + lx] = psi_of(ph.rho_ref + s, ph.psi_rho0, ph.inv_psi_rho0);
+    for (int k = 0; k < K; ++k) {
+      if (interior[k]) {
+        const Nbr nb = neighbours(lx[k], y0 + ly[k], z, nx, ny, nz, plane);
+        pull<T, R>(src, ps, nb, keep[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (interior[k]) {
+        R s = R(0);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) s += keep[k][q];
+        lp[(ly[k] + 1) * nx + lx[k]] = psi_of(ph.rho_ref + s, ph.psi_rho0, ph.inv_psi_rho0);
+      }
     }
     for (int h = tid; h < nhalo; h += NT) {
       const int hl = h < nx ? -1 : bye;
@@ -386,7 +405,7 @@ k_step(const T* __restrict__ src, T* __restrict__ dst, StepArgs a) {
       hy = hy < 0 ? hy + ny : (hy >= ny ? hy - ny : hy);
       const Nbr nb = neighbours(hx, hy, z, nx, ny, nz, plane);
       const R s = pull_sum<T, R>(src, ps, nb);
-      lp[(hl + 1) * row_pitch + hx] = psi_of(ph.rho_ref + s, ph.psi_rho0, ph.inv_psi_rho0);
+      lp[(hl + 1) * nx + hx] = psi_of(ph.rho_ref + s, ph.psi_rho0, ph.inv_psi_rho0);
     }
   };
 
@@ -394,41 +413,46 @@ k_step(const T* __restrict__ src, T* __restrict__ dst, StepArgs a) {
   load_plane(zprev, 0, nxt);
   load_plane(z0, 1, cur);
 
-  for (int z = z0, k = 0; z < z1; ++z, ++k) {
+  for (int z = z0, it = 0; z < z1; ++z, ++it) {
     const int znext = z == nz - 1 ? 0 : z + 1;
-    load_plane(znext, (k + 2) & 3, nxt);
+    load_plane(znext, (it + 2) & 3, nxt);
     __syncthreads();
-    if (interior) {
-      const R* pm = lds + (k & 3) * lplane;
-      const R* pc = lds + ((k + 1) & 3) * lplane;
-      const R* pp = lds + ((k + 2) & 3) * lplane;
-      const int xm = lx == 0 ? nx - 1 : lx - 1;
-      const int xp = lx == nx - 1 ? 0 : lx + 1;
-      const int rm = ly * row_pitch, rc = (ly + 1) * row_pitch, rp = (ly + 2) * row_pitch;
+    const R* pm = lds + (it & 3) * lplane;
+    const R* pc = lds + ((it + 1) & 3) * lplane;
+    const R* pp = lds + ((it + 2) & 3) * lplane;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (!interior[k]) continue;
+      const int x = lx[k];
+      const int xm = x == 0 ? nx - 1 : x - 1;
+      const int xp = x == nx - 1 ? 0 : x + 1;
+      const int rm = ly[k] * nx, rc = (ly[k] + 1) * nx, rp = (ly[k] + 2) * nx;
       // sum_a w_a psi(x + c_a) c_a, axis links weight 1/18, diagonals 1/36.
       const R ax = pc[rc + xp] - pc[rc + xm];
-      const R ay = pc[rp + lx] - pc[rm + lx];
-      const R az = pp[rc + lx] - pm[rc + lx];
+      const R ay = pc[rp + x] - pc[rm + x];
+      const R az = pp[rc + x] - pm[rc + x];
       const R dxy = pc[rp + xp] - pc[rm + xm];   // (+,+) minus (-,-)
       const R dxmy = pc[rm + xp] - pc[rp + xm];  // (+,-) minus (-,+)
       const R dxz = pp[rc + xp] - pm[rc + xm];
       const R dxmz = pm[rc + xp] - pp[rc + xm];
-      const R dyz = pp[rp + lx] - pm[rm + lx];
-      const R dymz = pm[rp + lx] - pp[rm + lx];
+      const R dyz = pp[rp + x] - pm[rm + x];
+      const R dymz = pm[rp + x] - pp[rm + x];
       const R sx = ax * R(1.0 / 18.0) + (dxy + dxmy + dxz + dxmz) * R(1.0 / 36.0);
       const R sy = ay * R(1.0 / 18.0) + (dxy - dxmy + dyz + dymz) * R(1.0 / 36.0);
       const R sz = az * R(1.0 / 18.0) + (dxz - dxmz + dyz - dymz) * R(1.0 / 36.0);
-      const R gpsi = -ph.G * pc[rc + lx];
-      collide<R, COLL, FORC>(cur, gpsi * sx, gpsi * sy, gpsi * sz, ph);
-      const unsigned idx = (unsigned)z * (unsigned)plane + (unsigned)(gy * nx + lx);
+      const R gpsi = -ph.G * pc[rc + x];
+      collide<R, COLL, FORC>(cur[k], gpsi * sx, gpsi * sy, gpsi * sz, ph);
+      const unsigned idx = (unsigned)z * (unsigned)plane + (unsigned)((y0 + ly[k]) * nx + x);
       // Written once and read only in the next step: non-temporal stores keep
       // them from evicting the rows the neighbouring tiles still re-read.
 #pragma unroll
       for (int q = 0; q < Q; ++q)
-        __builtin_nontemporal_store(T(cur[q]), &dst[(long long)q * ps + idx]);
+        __builtin_nontemporal_store(T(cur[k][q]), &dst[(long long)q * ps + idx]);
     }
 #pragma unroll
-    for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int q = 0; q < Q; ++q) cur[k][q] = nxt[k][q];
   }
 }
 
@@ -706,38 +730,41 @@ hipError_t launch_init(int prec, void* lat, const double* rho0, const StepArgs& 
   return hipGetLastError();
 }
 
+template <class T, int COLL, int FORC, int NT>
+static void step_nt(int npt, int grid, size_t lds, const T* in, T* out, const StepArgs& a,
+                    hipStream_t s) {
+  if (npt == 2)
+    hipLaunchKernelGGL((k_step<T, COLL, FORC, NT, 2>), dim3(grid), dim3(NT), lds, s, in, out, a);
+  else
+    hipLaunchKernelGGL((k_step<T, COLL, FORC, NT, 1>), dim3(grid), dim3(NT), lds, s, in, out, a);
+}
+
 template <class T, int COLL, int FORC>
-static hipError_t step_t(int threads, const void* src, void* dst, const StepArgs& a,
+static hipError_t step_t(int threads, int npt, const void* src, void* dst, const StepArgs& a,
                          hipStream_t s) {
   const int grid = a.ntiles_y * ((a.nz + a.zchunk - 1) / a.zchunk);
   const size_t lds = (size_t)4 * (a.by + 2) * a.nx * sizeof(T);
+  if ((long long)a.by * a.nx > (long long)npt * threads) return hipErrorInvalidValue;
   const T* in = (const T*)src;
   T* out = (T*)dst;
   switch (threads) {
-    case 256:
-      hipLaunchKernelGGL((k_step<T, COLL, FORC, 256>), dim3(grid), dim3(256), lds, s, in, out, a);
-      break;
-    case 512:
-      hipLaunchKernelGGL((k_step<T, COLL, FORC, 512>), dim3(grid), dim3(512), lds, s, in, out, a);
-      break;
-    default:
-      hipLaunchKernelGGL((k_step<T, COLL, FORC, 1024>), dim3(grid), dim3(1024), lds, s, in, out,
-                         a);
-      break;
+    case 256: step_nt<T, COLL, FORC, 256>(npt, grid, lds, in, out, a, s); break;
+    case 512: step_nt<T, COLL, FORC, 512>(npt, grid, lds, in, out, a, s); break;
+    default: step_nt<T, COLL, FORC, 1024>(npt, grid, lds, in, out, a, s); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_step(int prec, int coll, int forc, int threads, const void* src, void* dst,
-                       const StepArgs& a, hipStream_t s) {
+hipError_t launch_step(int prec, int coll, int forc, int threads, int npt, const void* src,
+                       void* dst, const StepArgs& a, hipStream_t s) {
   if (prec == 0) {
-    if (coll == kMRT) return step_t<double, kMRT, kGuo>(threads, src, dst, a, s);
-    if (forc == kShift) return step_t<double, kBGK, kShift>(threads, src, dst, a, s);
-    return step_t<double, kBGK, kGuo>(threads, src, dst, a, s);
+    if (coll == kMRT) return step_t<double, kMRT, kGuo>(threads, npt, src, dst, a, s);
+    if (forc == kShift) return step_t<double, kBGK, kShift>(threads, npt, src, dst, a, s);
+    return step_t<double, kBGK, kGuo>(threads, npt, src, dst, a, s);
   }
-  if (coll == kMRT) return step_t<float, kMRT, kGuo>(threads, src, dst, a, s);
-  if (forc == kShift) return step_t<float, kBGK, kShift>(threads, src, dst, a, s);
-  return step_t<float, kBGK, kGuo>(threads, src, dst, a, s);
+  if (coll == kMRT) return step_t<float, kMRT, kGuo>(threads, npt, src, dst, a, s);
+  if (forc == kShift) return step_t<float, kBGK, kShift>(threads, npt, src, dst, a, s);
+  return step_t<float, kBGK, kGuo>(threads, npt, src, dst, a, s);
 }
 
 hipError_t launch_moments(int prec, const void* lat, double* rho, double* u, double* p,

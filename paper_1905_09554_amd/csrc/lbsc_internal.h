@@ -28,8 +28,8 @@ enum Forc { kGuo = 0, kShift = 1 };
 // Launchers; all queue work on `s` and return the launch status.
 hipError_t launch_init(int prec, void* lat, const double* rho0_dev, const StepArgs& a,
                        hipStream_t s);
-hipError_t launch_step(int prec, int coll, int forc, int threads, const void* src, void* dst,
-                       const StepArgs& a, hipStream_t s);
+hipError_t launch_step(int prec, int coll, int forc, int threads, int npt, const void* src,
+                       void* dst, const StepArgs& a, hipStream_t s);
 hipError_t launch_moments(int prec, const void* lat, double* rho, double* u, double* p,
                           const StepArgs& a, hipStream_t s);
 // Diagnostics: partials holds diag_blocks(a) * 8 doubles; out holds 4 + nz.

@@ -96,6 +96,8 @@ def test_config1_f32_shifted_1000_steps(coll, rho_ref):
 @pytest.mark.parametrize("shape,tuning", [
     ((36, 20, 18), dict(threads=256, block_y=3, z_chunk=5)),
     ((36, 20, 18), dict(threads=1024, z_chunk=7, xcd_remap=0)),
+    ((36, 20, 18), dict(threads=256, nodes_per_thread=2, z_chunk=4)),
+    ((100, 9, 11), dict(threads=256, nodes_per_thread=2, block_y=3, z_chunk=3)),
     ((1, 1, 32), None),
     ((24, 24, 1), dict(threads=512, z_chunk=1)),
     ((7, 5, 3), dict(threads=256, block_y=2, z_chunk=2)),
@@ -116,7 +118,9 @@ def test_launch_shape_does_not_change_results_bitwise(precision):
     rho0 = gc.ligament(40, 36, 30, 8.0, 0.1, 1, noise=1e-4)
     ref = None
     for t in (None, dict(threads=256, z_chunk=3), dict(threads=512, block_y=1, z_chunk=30),
-              dict(threads=1024, xcd_remap=0, z_chunk=4), dict(threads=1024, block_y=5)):
+              dict(threads=1024, xcd_remap=0, z_chunk=4), dict(threads=1024, block_y=5),
+              dict(threads=256, nodes_per_thread=2, z_chunk=6),
+              dict(threads=512, nodes_per_thread=2, pop_pad=0)):
         g = gc.run_gpu(rho0, 9, collision="mrt", precision=precision, tuning=t)
         if ref is None:
             ref = g["state"]
