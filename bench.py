@@ -113,6 +113,38 @@ def run_gpu(rho0, info, precision, steps, warmup):
     }
 
 
+def run_batch(steps, warmup):
+    """The 64-ligament dispersion sweep (uneven boxes, 3.9e8 nodes) in one
+    batch: MLUPS with one launch per step and with one persistent launch."""
+    import torch
+    from paper_1905_09554_amd import dispersion
+
+    sweep = dispersion.make_sweep(seed=0)
+    total = sum(m["rho0"].size for m in sweep["members"])
+    out = {"workload": sweep["workload"], "members": len(sweep["members"]), "nodes": total,
+           "dtype": sweep["precision"], "collision": sweep["collision"]}
+    b = dispersion.build_batch(sweep)
+    for mode in (0, 1):
+        b.set_tuning(**dict(b.get_tuning(), persistent=mode))
+        b.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        key = "persistent" if mode else "per_step_launch"
+        out[key] = {"value": round(total * steps / dt / 1e6, 1), "unit": "MLUPS",
+                    "ms_per_step": round(dt / steps * 1e3, 4),
+                    "hbm_frac_alg": round(total * steps / dt * BYTES_PER_NODE["f32"] / 1e9
+                                          / HBM_PEAK_GBS, 4)}
+    out["steps"] = steps
+    out["tuning"] = b.get_tuning()
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(rho0, info, nz_sample=16, steps=40):
     """The float64 oracle on the host: the first nz_sample planes of the same
     input as a periodic slab, `steps` steps, reported in MLUPS."""
@@ -143,6 +175,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 figure")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched sweep figure")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the step is single-GPU; see the design notes "
@@ -163,6 +196,10 @@ def main():
     if not args.no_fp64:
         f64 = run_gpu(rho0, info, "f64", max(50, args.steps // 2), args.warmup)
         print("f64 done: %.0f MLUPS" % f64["mlups"], file=sys.stderr, flush=True)
+    batch = None
+    if not args.no_batch:
+        batch = run_batch(max(20, args.steps // 5), 5)
+        print("batch done: %.0f MLUPS" % batch["persistent"]["value"], file=sys.stderr, flush=True)
     cpu = None if args.no_cpu_baseline else cpu_baseline(rho0, info)
 
     nz, ny, nx = rho0.shape
@@ -194,6 +231,8 @@ def main():
                         "ms_per_step": round(f64["ms_per_step"], 4),
                         "kernel_ms": round(f64["kernel_ms"], 4), "roofline": f64["roofline"],
                         "tuning": f64["tuning"]}
+    if batch:
+        line["batched"] = batch
     print(json.dumps(line), flush=True)
 
 

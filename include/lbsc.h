@@ -93,6 +93,8 @@ typedef struct lbsc_tuning {
   int32_t block_y;     /* rows per tile; 0 = as many as the work-group holds  */
   int32_t pop_pad;     /* extra elements between population arrays, <= 65536 */
   int32_t nodes_per_thread; /* interior nodes each thread carries: 1 or 2      */
+  int32_t persistent;  /* 1: all steps of one lbsc_step call in one cooperative
+                          launch with grid barriers; 0: one launch per step   */
 } lbsc_tuning;
 
 /* Bytes of device memory a context with these parameters needs: two
@@ -148,6 +150,43 @@ int lbsc_get_state(lbsc_ctx* c, void* host, size_t bytes, int64_t* step);
  * the step counter; resuming from a saved state is bitwise identical to an
  * uninterrupted run.  Synchronises the stream. */
 int lbsc_set_state(lbsc_ctx* c, const void* host, size_t bytes, int64_t step);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent periodic boxes (e.g. ligaments of uneven radius and
+ * wavenumber for a dispersion sweep, Sec. 4 and Fig. 3 of the paper) stepped
+ * together: one launch per step covers the tiles of every member, or, with
+ * lbsc_tuning.persistent = 1, one cooperative launch runs all steps of an
+ * lbsc_step call with a grid-wide barrier between steps (bounded wait: a
+ * barrier that does not complete within about a second makes lbsc_step return
+ * LBSC_EHIP instead of hanging).  Members share precision, collision and
+ * forcing; box size, G, tau, rates and rho_ref may differ.  Each member's
+ * result is bitwise identical to running it alone.
+ */
+
+/* Device bytes for a batch of n members (params[n]); 0 if invalid. */
+size_t lbsc_batch_state_bytes(int32_t n, const lbsc_params* params);
+
+/* Creates a batch context.  rho0_host[i]: member i's nx*ny*nz float64
+ * densities (host, copied, finite and > 0).  dev_buf: >=
+ * lbsc_batch_state_bytes bytes, 256-byte aligned, borrowed.  The calls for a
+ * single box (lbsc_step, lbsc_get_tuning, ...) act on the whole batch or, for
+ * per-box outputs, on member 0.  Synchronises the stream. */
+int lbsc_init_batch(lbsc_ctx** out, int32_t n, const lbsc_params* params,
+                    const double* const* rho0_host, void* dev_buf, size_t dev_bytes,
+                    void* hip_stream);
+
+/* Number of members (1 for a context from lbsc_init_fields). */
+int32_t lbsc_batch_size(const lbsc_ctx* c);
+
+/* Per-member versions of lbsc_compute_moments, lbsc_interface_diagnostics,
+ * lbsc_get_state and lbsc_set_state (same arguments and layouts; member is
+ * 0-based; the step counter is shared by all members). */
+int lbsc_member_moments(lbsc_ctx* c, int32_t member, double* rho_dev, double* u_dev,
+                        double* p_dev);
+int lbsc_member_diagnostics(lbsc_ctx* c, int32_t member, double rho_v, double rho_l,
+                            lbsc_diag* out, double* r_of_z_host);
+int lbsc_member_get_state(lbsc_ctx* c, int32_t member, void* host, size_t bytes);
+int lbsc_member_set_state(lbsc_ctx* c, int32_t member, const void* host, size_t bytes);
 
 /* Overrides the launch shape of the fused step (see lbsc_tuning). */
 int lbsc_set_tuning(lbsc_ctx* c, const lbsc_tuning* t);

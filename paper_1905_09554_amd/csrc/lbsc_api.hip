@@ -3,13 +3,23 @@
 // Validation, the context, the device-memory layout inside the caller's
 // buffer, and the order of launches.  All arithmetic of the method runs in the
 // kernels of lbsc_device.hip.
+//
+// A context holds one or more members (boxes).  lbsc_init_fields makes a
+// context of one member; lbsc_init_batch makes several, stepped together by
+// one launch per step (or one cooperative launch for all steps).
+//
+// Caller buffer layout:
+//   [member 0: lattice 0 | lattice 1] [member 1: ...] ... [aux]
+//   aux = member table | tile table | barrier words | diagnostic partials |
+//         diagnostic results
+// A single box reserves room for a population padding of up to kMaxPad so
+// its layout can be retuned in place; batch members use the default pad.
 #include "lbsc.h"
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
-#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -17,17 +27,32 @@
 
 #include "lbsc_internal.h"
 
-struct lbsc_ctx {
+namespace {
+
+struct Member {
   lbsc_params p;
   lbsc::StepArgs a;
+  void* lat[2];
+  size_t lat_bytes;  // capacity of each lattice
+};
+
+}  // namespace
+
+struct lbsc_ctx {
+  std::vector<Member> m;
+  bool batch;
   lbsc_tuning tune;
   hipStream_t stream;
   char* buf;
   size_t bytes;
-  void* lat[2];
-  int cur;           // lattice holding the current state
-  double* part;      // diagnostic partial sums
-  double* dout;      // diagnostic results: 4 + nz doubles
+  int cur;                       // lattice holding the current state
+  lbsc::BatchMember* dmembers;   // device member table
+  int4* dtiles;                  // device tile table
+  int ntiles;
+  long long tile_cap;
+  unsigned* dsync;               // grid-barrier words (count, generation, error)
+  double* part;                  // diagnostic partial sums
+  double* dout;                  // diagnostic results: 4 + max nz doubles
   int64_t step;
   std::string err;
 };
@@ -37,13 +62,16 @@ namespace {
 thread_local std::string g_init_err;
 
 constexpr size_t kAlign = 256;
-// Largest padding between population arrays (elements); the state buffer is
-// sized for it so the layout can be retuned in place.
+// Largest padding between population arrays (elements); a single box's
+// buffer is sized for it so the layout can be retuned in place.
 constexpr long long kMaxPad = 65536;
 constexpr long long kDefaultPad = 1088;
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+// Polls of a grid barrier before it reports a timeout (about a second).
+constexpr unsigned kSpinLimit = 1u << 23;
 
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 size_t elem_size(const lbsc_params& p) { return p.precision == LBSC_F64 ? 8 : 4; }
+long long nodes(const lbsc_params& p) { return (long long)p.nx * p.ny * p.nz; }
 
 int fail(std::string* where, int code, const std::string& msg) {
   if (where) *where = msg;
@@ -56,8 +84,7 @@ int check_params(const lbsc_params* p, std::string* msg) {
   if (p->nx < 1 || p->ny < 1 || p->nz < 1)
     return fail(msg, LBSC_EINVAL, "box dimensions must be >= 1");
   if (p->nx > 1024) return fail(msg, LBSC_EINVAL, "nx > 1024 is not supported (full-row tiles)");
-  const long long n = (long long)p->nx * p->ny * p->nz;
-  if (n > 0x7fffffffLL) return fail(msg, LBSC_EINVAL, "more than 2^31 - 1 nodes");
+  if (nodes(*p) > 0x7fffffffLL) return fail(msg, LBSC_EINVAL, "more than 2^31 - 1 nodes");
   if (p->collision != LBSC_BGK && p->collision != LBSC_MRT)
     return fail(msg, LBSC_EINVAL, "collision must be LBSC_BGK or LBSC_MRT");
   if (p->forcing != LBSC_FORCING_GUO && p->forcing != LBSC_FORCING_SHIFT)
@@ -81,14 +108,30 @@ int check_params(const lbsc_params* p, std::string* msg) {
   return LBSC_OK;
 }
 
-lbsc::StepArgs make_args(const lbsc_params& p, const lbsc_tuning& t) {
+// Checks a batch: every member valid, one kernel family for all.
+int check_batch(int32_t n, const lbsc_params* p, std::string* msg) {
+  if (n < 1) return fail(msg, LBSC_EINVAL, "batch size must be >= 1");
+  if (!p) return fail(msg, LBSC_EINVAL, "params is NULL");
+  for (int32_t i = 0; i < n; ++i) {
+    std::string m;
+    if (check_params(&p[i], &m) != LBSC_OK)
+      return fail(msg, LBSC_EINVAL, "member " + std::to_string(i) + ": " + m);
+    if (p[i].precision != p[0].precision || p[i].collision != p[0].collision ||
+        p[i].forcing != p[0].forcing)
+      return fail(msg, LBSC_EINVAL,
+                  "member " + std::to_string(i) + ": precision, collision and forcing must match");
+  }
+  return LBSC_OK;
+}
+
+lbsc::StepArgs make_args(const lbsc_params& p, const lbsc_tuning& t, long long pad) {
   lbsc::StepArgs a;
   a.nx = p.nx;
   a.ny = p.ny;
   a.nz = p.nz;
   a.plane = p.nx * p.ny;
-  a.n = (long long)p.nx * p.ny * p.nz;
-  a.ps = (a.n + 63) / 64 * 64 + (t.pop_pad >= 0 ? t.pop_pad : kDefaultPad);
+  a.n = nodes(p);
+  a.ps = (a.n + 63) / 64 * 64 + pad;
   const int rows = t.nodes_per_thread * t.threads / p.nx;  // rows the group can hold
   int by = t.block_y > 0 ? t.block_y : rows;
   if (by > rows) by = rows;
@@ -110,36 +153,73 @@ lbsc::StepArgs make_args(const lbsc_params& p, const lbsc_tuning& t) {
   return a;
 }
 
-lbsc_tuning default_tuning(const lbsc_params& p) {
+long long pad_of(const lbsc_tuning& t) { return t.pop_pad >= 0 ? t.pop_pad : kDefaultPad; }
+
+lbsc_tuning default_tuning(const lbsc_params* p, int32_t n) {
+  int nx = 1, ny = 1;
+  long long work = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    nx = std::max(nx, p[i].nx);
+    ny = std::max(ny, p[i].ny);
+    work += (long long)p[i].ny * p[i].nz;
+  }
   lbsc_tuning t;
   // Two or more work-groups per CU overlap one group's loads with another's
   // collision; float64 needs twice the registers, so smaller groups.
-  t.threads = p.precision == LBSC_F64 ? 256 : 512;
-  while (t.threads < p.nx) t.threads *= 2;
+  t.threads = p[0].precision == LBSC_F64 ? 256 : 512;
+  while (t.threads < nx) t.threads *= 2;
   t.block_y = 0;
   t.xcd_remap = 1;
   t.pop_pad = -1;
   t.nodes_per_thread = 1;
+  t.persistent = 0;
   // Enough work-groups to fill 256 CUs a few times over, but long z-marches
   // so the two extra halo planes of each chunk stay a small fraction.
-  const int by = std::max(1, std::min(p.ny, t.nodes_per_thread * t.threads / p.nx));
-  const long long tiles = (p.ny + by - 1) / by;
-  long long zc = (tiles * p.nz + 2047) / 2048;
+  const int by = std::max(1, std::min(ny, t.threads / nx));
+  long long zc = (work / by + 2047) / 2048;
   if (zc < 8) zc = 8;
   if (zc > 64) zc = 64;
-  if (zc > p.nz) zc = p.nz;
   t.z_chunk = (int)zc;
   return t;
 }
 
-size_t lattice_bytes(const lbsc_params& p) {
-  const long long n = (long long)p.nx * p.ny * p.nz;
-  return align_up((size_t)lbsc::Q * (size_t)((n + 63) / 64 * 64 + kMaxPad) * elem_size(p));
+size_t lattice_bytes(const lbsc_params& p, long long pad) {
+  return align_up((size_t)lbsc::Q * (size_t)((nodes(p) + 63) / 64 * 64 + pad) * elem_size(p));
 }
 
-size_t aux_bytes(const lbsc_params& p, const lbsc::StepArgs& a) {
-  return align_up((size_t)lbsc::diag_blocks(a) * 8 * sizeof(double)) +
-         align_up((size_t)(4 + p.nz) * sizeof(double));
+// Sizes of the aux area (tile capacity: one tile per row and plane, the
+// finest possible tiling).
+struct AuxSizes {
+  size_t members, tiles, sync, part, out, total;
+  long long tile_cap;
+};
+
+AuxSizes aux_sizes(int32_t n, const lbsc_params* p) {
+  AuxSizes s;
+  long long cap = 0;
+  int max_blocks = 0, max_nz = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    cap += (long long)p[i].ny * p[i].nz;
+    lbsc::StepArgs a;
+    a.plane = p[i].nx * p[i].ny;
+    a.nz = p[i].nz;
+    max_blocks = std::max(max_blocks, lbsc::diag_blocks(a));
+    max_nz = std::max(max_nz, p[i].nz);
+  }
+  s.tile_cap = cap;
+  s.members = align_up((size_t)n * sizeof(lbsc::BatchMember));
+  s.tiles = align_up((size_t)cap * sizeof(int4));
+  s.sync = kAlign;
+  s.part = align_up((size_t)max_blocks * 8 * sizeof(double));
+  s.out = align_up((size_t)(4 + max_nz) * sizeof(double));
+  s.total = s.members + s.tiles + s.sync + s.part + s.out;
+  return s;
+}
+
+size_t batch_bytes(int32_t n, const lbsc_params* p, long long pad) {
+  size_t total = 0;
+  for (int32_t i = 0; i < n; ++i) total += 2 * lattice_bytes(p[i], pad);
+  return total + aux_sizes(n, p).total;
 }
 
 int hip_fail(lbsc_ctx* c, hipError_t e, const char* what) {
@@ -147,45 +227,65 @@ int hip_fail(lbsc_ctx* c, hipError_t e, const char* what) {
   return LBSC_EHIP;
 }
 
-#define HIP_OR_FAIL(ctx, expr)                          \
-  do {                                                  \
-    hipError_t _e = (expr);                             \
-    if (_e != hipSuccess) return hip_fail(ctx, _e, #expr); \
+#define HIP_OR_FAIL(ctx, expr)                              \
+  do {                                                      \
+    hipError_t _e = (expr);                                 \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, #expr);  \
   } while (0)
 
-}  // namespace
-
-extern "C" {
-
-size_t lbsc_state_bytes(const lbsc_params* p) {
-  if (check_params(p, nullptr) != LBSC_OK) return 0;
-  const lbsc_tuning t = default_tuning(*p);
-  const lbsc::StepArgs a = make_args(*p, t);
-  return 2 * lattice_bytes(*p) + aux_bytes(*p, a);
+// Recomputes every member's tile list and uploads the member and tile tables
+// (synchronously).
+int rebuild_tables(lbsc_ctx* c) {
+  std::vector<lbsc::BatchMember> hm(c->m.size());
+  std::vector<int4> ht;
+  for (size_t i = 0; i < c->m.size(); ++i) {
+    const lbsc::StepArgs& a = c->m[i].a;
+    hm[i].a = a;
+    hm[i].lat[0] = c->m[i].lat[0];
+    hm[i].lat[1] = c->m[i].lat[1];
+    const int nchunks = (a.nz + a.zchunk - 1) / a.zchunk;
+    for (int zc = 0; zc < nchunks; ++zc)
+      for (int ty = 0; ty < a.ntiles_y; ++ty) ht.push_back(make_int4((int)i, ty, zc, 0));
+  }
+  if ((long long)ht.size() > c->tile_cap)
+    return fail(&c->err, LBSC_EINVAL, "tile table exceeds its capacity");
+  c->ntiles = (int)ht.size();
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->dmembers, hm.data(), hm.size() * sizeof(hm[0]),
+                                hipMemcpyHostToDevice, c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->dtiles, ht.data(), ht.size() * sizeof(ht[0]),
+                                hipMemcpyHostToDevice, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return LBSC_OK;
 }
 
-int lbsc_init_fields(lbsc_ctx** out, const lbsc_params* p, const double* rho0_host,
-                     void* dev_buf, size_t dev_bytes, void* hip_stream) {
+// Shared by lbsc_init_fields and lbsc_init_batch.
+int create(lbsc_ctx** out, int32_t n, const lbsc_params* p, const double* const* rho0,
+           void* dev_buf, size_t dev_bytes, void* hip_stream, bool batch) {
   g_init_err.clear();
   if (!out) return fail(&g_init_err, LBSC_EINVAL, "out is NULL");
   *out = nullptr;
-  int rc = check_params(p, &g_init_err);
+  int rc = check_batch(n, p, &g_init_err);
   if (rc != LBSC_OK) return rc;
-  if (!rho0_host) return fail(&g_init_err, LBSC_EINVAL, "rho0_host is NULL");
+  if (!rho0) return fail(&g_init_err, LBSC_EINVAL, "rho0_host is NULL");
   if (!dev_buf) return fail(&g_init_err, LBSC_EINVAL, "dev_buf is NULL");
   if (((uintptr_t)dev_buf) % kAlign != 0)
     return fail(&g_init_err, LBSC_EINVAL, "dev_buf must be 256-byte aligned");
-  const size_t need = lbsc_state_bytes(p);
+  const long long pad = batch ? kDefaultPad : kMaxPad;
+  const size_t need = batch_bytes(n, p, pad);
   if (dev_bytes < need)
     return fail(&g_init_err, LBSC_EINVAL,
-                "dev_bytes " + std::to_string(dev_bytes) + " < lbsc_state_bytes " +
-                    std::to_string(need));
-  const long long n = (long long)p->nx * p->ny * p->nz;
-  for (long long i = 0; i < n; ++i) {
-    const double r = rho0_host[i];
-    if (!(std::isfinite(r) && r > 0))
-      return fail(&g_init_err, LBSC_EINVAL,
-                  "rho0 must be finite and > 0 (index " + std::to_string(i) + ")");
+                "dev_bytes " + std::to_string(dev_bytes) + " < required " + std::to_string(need));
+  for (int32_t m = 0; m < n; ++m) {
+    if (!rho0[m])
+      return fail(&g_init_err, LBSC_EINVAL, "rho0 of member " + std::to_string(m) + " is NULL");
+    const long long nn = nodes(p[m]);
+    for (long long i = 0; i < nn; ++i) {
+      const double r = rho0[m][i];
+      if (!(std::isfinite(r) && r > 0))
+        return fail(&g_init_err, LBSC_EINVAL,
+                    "rho0 must be finite and > 0 (member " + std::to_string(m) + ", index " +
+                        std::to_string(i) + ")");
+    }
   }
   hipPointerAttribute_t attr;
   if (hipPointerGetAttributes(&attr, dev_buf) != hipSuccess || attr.type != hipMemoryTypeDevice) {
@@ -195,71 +295,133 @@ int lbsc_init_fields(lbsc_ctx** out, const lbsc_params* p, const double* rho0_ho
 
   lbsc_ctx* c = new (std::nothrow) lbsc_ctx();
   if (!c) return fail(&g_init_err, LBSC_ENOMEM, "context allocation failed");
-  c->p = *p;
-  c->tune = default_tuning(*p);
-  c->a = make_args(*p, c->tune);
+  c->batch = batch;
+  c->tune = default_tuning(p, n);
   c->stream = (hipStream_t)hip_stream;
   c->buf = (char*)dev_buf;
   c->bytes = dev_bytes;
-  const size_t lb = lattice_bytes(*p);
-  c->lat[0] = c->buf;
-  c->lat[1] = c->buf + lb;
-  c->part = (double*)(c->buf + 2 * lb);
-  c->dout = (double*)(c->buf + 2 * lb + align_up((size_t)lbsc::diag_blocks(c->a) * 8 * 8));
   c->cur = 0;
   c->step = 0;
+  c->m.resize(n);
+  size_t off = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    Member& mm = c->m[i];
+    mm.p = p[i];
+    mm.a = make_args(p[i], c->tune, kDefaultPad);
+    mm.lat_bytes = lattice_bytes(p[i], pad);
+    mm.lat[0] = c->buf + off;
+    mm.lat[1] = c->buf + off + mm.lat_bytes;
+    off += 2 * mm.lat_bytes;
+  }
+  const AuxSizes ax = aux_sizes(n, p);
+  c->tile_cap = ax.tile_cap;
+  c->dmembers = (lbsc::BatchMember*)(c->buf + off);
+  off += ax.members;
+  c->dtiles = (int4*)(c->buf + off);
+  off += ax.tiles;
+  c->dsync = (unsigned*)(c->buf + off);
+  off += ax.sync;
+  c->part = (double*)(c->buf + off);
+  off += ax.part;
+  c->dout = (double*)(c->buf + off);
 
-  // Stage rho0 in the second lattice (19 N values >= N doubles), then build
-  // the state in the first.
-  hipError_t e = hipMemcpyAsync(c->lat[1], rho0_host, (size_t)n * sizeof(double),
-                                hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = lbsc::launch_init(p->precision, c->lat[0], (const double*)c->lat[1],
-                                             c->a, c->stream);
+  // Stage each rho0 in the member's second lattice (19 N values >= N
+  // doubles), then build the state in the first.
+  hipError_t e = hipSuccess;
+  for (int32_t i = 0; i < n && e == hipSuccess; ++i) {
+    Member& mm = c->m[i];
+    e = hipMemcpyAsync(mm.lat[1], rho0[i], (size_t)nodes(mm.p) * sizeof(double),
+                       hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+      e = lbsc::launch_init(mm.p.precision, mm.lat[0], (const double*)mm.lat[1], mm.a, c->stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     g_init_err = std::string("initialisation failed: ") + hipGetErrorString(e);
     delete c;
     return LBSC_EHIP;
   }
+  rc = rebuild_tables(c);
+  if (rc != LBSC_OK) {
+    g_init_err = c->err;
+    delete c;
+    return rc;
+  }
   *out = c;
   return LBSC_OK;
 }
 
-int lbsc_step(lbsc_ctx* c, int64_t nsteps) {
-  if (!c) return LBSC_EINVAL;
-  if (nsteps < 0) return fail(&c->err, LBSC_EINVAL, "nsteps must be >= 0");
+Member* member(lbsc_ctx* c, int32_t i) {
+  if (!c) return nullptr;
+  if (i < 0 || i >= (int32_t)c->m.size()) {
+    c->err = "member index out of range";
+    return nullptr;
+  }
+  return &c->m[i];
+}
+
+int step_batch(lbsc_ctx* c, int64_t nsteps) {
+  lbsc::BatchLaunch L;
+  const Member& m0 = c->m[0];
+  L.prec = m0.p.precision;
+  L.coll = m0.p.collision;
+  L.forc = m0.p.forcing;
+  L.threads = c->tune.threads;
+  L.npt = c->tune.nodes_per_thread;
+  L.members = c->dmembers;
+  L.tiles = c->dtiles;
+  L.ntiles = c->ntiles;
+  L.remap = c->tune.xcd_remap;
+  L.lds = 0;
+  for (const Member& mm : c->m)
+    L.lds = std::max(L.lds, (size_t)4 * (mm.a.by + 2) * mm.a.nx * elem_size(mm.p));
+  L.sync = c->dsync;
+  L.spin_limit = kSpinLimit;
+  if (c->tune.persistent) {
+    if (nsteps > 0x7fffffff) return fail(&c->err, LBSC_EINVAL, "too many steps for one launch");
+    L.persistent = 1;
+    L.parity = c->cur;
+    L.nsteps = (int)nsteps;
+    HIP_OR_FAIL(c, hipMemsetAsync(c->dsync, 0, 3 * sizeof(unsigned), c->stream));
+    HIP_OR_FAIL(c, lbsc::launch_batch(L, c->stream));
+    unsigned flags[3];
+    HIP_OR_FAIL(c, hipMemcpyAsync(flags, c->dsync, sizeof(flags), hipMemcpyDeviceToHost,
+                                  c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    if (flags[2]) return fail(&c->err, LBSC_EHIP, "grid barrier timed out in the persistent step");
+    if (nsteps & 1) c->cur ^= 1;
+    c->step += nsteps;
+    return LBSC_OK;
+  }
+  L.persistent = 0;
+  L.nsteps = 1;
   for (int64_t i = 0; i < nsteps; ++i) {
-    hipError_t e = lbsc::launch_step(c->p.precision, c->p.collision, c->p.forcing,
-                                     c->tune.threads, c->tune.nodes_per_thread, c->lat[c->cur],
-                                     c->lat[c->cur ^ 1], c->a, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "step launch");
+    L.parity = c->cur;
+    hipError_t e = lbsc::launch_batch(L, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "batched step launch");
     c->cur ^= 1;
     c->step += 1;
   }
   return LBSC_OK;
 }
 
-int64_t lbsc_step_count(const lbsc_ctx* c) { return c ? c->step : -1; }
-
-int lbsc_compute_moments(lbsc_ctx* c, double* rho_dev, double* u_dev, double* p_dev) {
-  if (!c) return LBSC_EINVAL;
+int moments_of(lbsc_ctx* c, Member* mm, double* rho_dev, double* u_dev, double* p_dev) {
   if (!rho_dev) return fail(&c->err, LBSC_EINVAL, "rho_dev is required");
-  hipError_t e = lbsc::launch_moments(c->p.precision, c->lat[c->cur], rho_dev, u_dev, p_dev, c->a,
-                                      c->stream);
+  hipError_t e = lbsc::launch_moments(mm->p.precision, mm->lat[c->cur], rho_dev, u_dev, p_dev,
+                                      mm->a, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "moments launch");
   return LBSC_OK;
 }
 
-int lbsc_interface_diagnostics(lbsc_ctx* c, double rho_v, double rho_l, lbsc_diag* out,
-                               double* r_of_z_host) {
-  if (!c) return LBSC_EINVAL;
+int diagnostics_of(lbsc_ctx* c, Member* mm, double rho_v, double rho_l, lbsc_diag* out,
+                   double* r_of_z_host) {
   if (!out) return fail(&c->err, LBSC_EINVAL, "out is NULL");
   if (!(std::isfinite(rho_v) && std::isfinite(rho_l) && rho_l > rho_v))
     return fail(&c->err, LBSC_EINVAL, "need finite rho_l > rho_v");
-  const int nz = c->p.nz;
-  hipError_t e = lbsc::launch_diagnostics(c->p.precision, c->lat[c->cur],
-                                          (double*)c->lat[c->cur ^ 1], c->part, c->dout, rho_v,
-                                          rho_l, c->a, c->stream);
+  const int nz = mm->p.nz;
+  hipError_t e = lbsc::launch_diagnostics(mm->p.precision, mm->lat[c->cur],
+                                          (double*)mm->lat[c->cur ^ 1], c->part, c->dout, rho_v,
+                                          rho_l, mm->a, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "diagnostics launch");
   std::vector<double> h(4 + (size_t)nz);
   HIP_OR_FAIL(c, hipMemcpyAsync(h.data(), c->dout, h.size() * sizeof(double),
@@ -287,47 +449,156 @@ int lbsc_interface_diagnostics(lbsc_ctx* c, double rho_v, double rho_l, lbsc_dia
   return LBSC_OK;
 }
 
-int lbsc_get_state(lbsc_ctx* c, void* host, size_t bytes, int64_t* step) {
-  if (!c) return LBSC_EINVAL;
-  const size_t need = (size_t)lbsc::Q * c->a.n * elem_size(c->p);
+int get_state_of(lbsc_ctx* c, Member* mm, void* host, size_t bytes) {
+  const size_t es = elem_size(mm->p);
+  const size_t need = (size_t)lbsc::Q * mm->a.n * es;
   if (!host || bytes != need)
     return fail(&c->err, LBSC_EINVAL, "host buffer must hold 19 * N values of the storage type");
-  const size_t es = elem_size(c->p);
-  hipError_t e = lbsc::launch_gather(c->p.precision, c->lat[c->cur], c->a.ps, c->lat[c->cur ^ 1],
-                                     c->a.ps, c->a, c->stream);
+  hipError_t e = lbsc::launch_gather(mm->p.precision, mm->lat[c->cur], mm->a.ps,
+                                     mm->lat[c->cur ^ 1], mm->a.ps, mm->a, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "gather launch");
-  HIP_OR_FAIL(c, hipMemcpy2DAsync(host, c->a.n * es, c->lat[c->cur ^ 1], c->a.ps * es, c->a.n * es,
-                                  lbsc::Q, hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(c, hipMemcpy2DAsync(host, mm->a.n * es, mm->lat[c->cur ^ 1], mm->a.ps * es,
+                                  mm->a.n * es, lbsc::Q, hipMemcpyDeviceToHost, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
-  if (step) *step = c->step;
   return LBSC_OK;
 }
 
-int lbsc_set_state(lbsc_ctx* c, const void* host, size_t bytes, int64_t step) {
-  if (!c) return LBSC_EINVAL;
-  const size_t need = (size_t)lbsc::Q * c->a.n * elem_size(c->p);
+int set_state_of(lbsc_ctx* c, Member* mm, const void* host, size_t bytes) {
+  const size_t es = elem_size(mm->p);
+  const size_t need = (size_t)lbsc::Q * mm->a.n * es;
   if (!host || bytes != need)
     return fail(&c->err, LBSC_EINVAL, "host buffer must hold 19 * N values of the storage type");
-  if (step < 0) return fail(&c->err, LBSC_EINVAL, "step must be >= 0");
-  const size_t es = elem_size(c->p);
-  HIP_OR_FAIL(c, hipMemcpy2DAsync(c->lat[c->cur ^ 1], c->a.ps * es, host, c->a.n * es, c->a.n * es,
-                                  lbsc::Q, hipMemcpyHostToDevice, c->stream));
-  hipError_t e = lbsc::launch_scatter(c->p.precision, c->lat[c->cur ^ 1], c->a.ps, c->lat[c->cur],
-                                      c->a.ps, c->a, c->stream);
+  HIP_OR_FAIL(c, hipMemcpy2DAsync(mm->lat[c->cur ^ 1], mm->a.ps * es, host, mm->a.n * es,
+                                  mm->a.n * es, lbsc::Q, hipMemcpyHostToDevice, c->stream));
+  hipError_t e = lbsc::launch_scatter(mm->p.precision, mm->lat[c->cur ^ 1], mm->a.ps,
+                                      mm->lat[c->cur], mm->a.ps, mm->a, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "scatter launch");
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
-  c->step = step;
   return LBSC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbsc_state_bytes(const lbsc_params* p) {
+  if (check_params(p, nullptr) != LBSC_OK) return 0;
+  return batch_bytes(1, p, kMaxPad);
+}
+
+size_t lbsc_batch_state_bytes(int32_t n, const lbsc_params* p) {
+  if (check_batch(n, p, nullptr) != LBSC_OK) return 0;
+  return batch_bytes(n, p, kDefaultPad);
+}
+
+int lbsc_init_fields(lbsc_ctx** out, const lbsc_params* p, const double* rho0_host,
+                     void* dev_buf, size_t dev_bytes, void* hip_stream) {
+  if (!rho0_host) {
+    g_init_err = "rho0_host is NULL";
+    if (out) *out = nullptr;
+    return LBSC_EINVAL;
+  }
+  const double* rho[1] = {rho0_host};
+  return create(out, 1, p, rho, dev_buf, dev_bytes, hip_stream, false);
+}
+
+int lbsc_init_batch(lbsc_ctx** out, int32_t n, const lbsc_params* p,
+                    const double* const* rho0_host, void* dev_buf, size_t dev_bytes,
+                    void* hip_stream) {
+  return create(out, n, p, rho0_host, dev_buf, dev_bytes, hip_stream, true);
+}
+
+int32_t lbsc_batch_size(const lbsc_ctx* c) { return c ? (int32_t)c->m.size() : -1; }
+
+int lbsc_step(lbsc_ctx* c, int64_t nsteps) {
+  if (!c) return LBSC_EINVAL;
+  if (nsteps < 0) return fail(&c->err, LBSC_EINVAL, "nsteps must be >= 0");
+  if (nsteps == 0) return LBSC_OK;
+  if (c->batch || c->tune.persistent) return step_batch(c, nsteps);
+  Member& m0 = c->m[0];
+  for (int64_t i = 0; i < nsteps; ++i) {
+    hipError_t e = lbsc::launch_step(m0.p.precision, m0.p.collision, m0.p.forcing,
+                                     c->tune.threads, c->tune.nodes_per_thread, m0.lat[c->cur],
+                                     m0.lat[c->cur ^ 1], m0.a, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "step launch");
+    c->cur ^= 1;
+    c->step += 1;
+  }
+  return LBSC_OK;
+}
+
+int64_t lbsc_step_count(const lbsc_ctx* c) { return c ? c->step : -1; }
+
+int lbsc_compute_moments(lbsc_ctx* c, double* rho_dev, double* u_dev, double* p_dev) {
+  Member* mm = member(c, 0);
+  if (!mm) return LBSC_EINVAL;
+  return moments_of(c, mm, rho_dev, u_dev, p_dev);
+}
+
+int lbsc_member_moments(lbsc_ctx* c, int32_t i, double* rho_dev, double* u_dev, double* p_dev) {
+  Member* mm = member(c, i);
+  if (!mm) return LBSC_EINVAL;
+  return moments_of(c, mm, rho_dev, u_dev, p_dev);
+}
+
+int lbsc_interface_diagnostics(lbsc_ctx* c, double rho_v, double rho_l, lbsc_diag* out,
+                               double* r_of_z_host) {
+  Member* mm = member(c, 0);
+  if (!mm) return LBSC_EINVAL;
+  return diagnostics_of(c, mm, rho_v, rho_l, out, r_of_z_host);
+}
+
+int lbsc_member_diagnostics(lbsc_ctx* c, int32_t i, double rho_v, double rho_l, lbsc_diag* out,
+                            double* r_of_z_host) {
+  Member* mm = member(c, i);
+  if (!mm) return LBSC_EINVAL;
+  return diagnostics_of(c, mm, rho_v, rho_l, out, r_of_z_host);
+}
+
+int lbsc_get_state(lbsc_ctx* c, void* host, size_t bytes, int64_t* step) {
+  Member* mm = member(c, 0);
+  if (!mm) return LBSC_EINVAL;
+  const int rc = get_state_of(c, mm, host, bytes);
+  if (rc == LBSC_OK && step) *step = c->step;
+  return rc;
+}
+
+int lbsc_member_get_state(lbsc_ctx* c, int32_t i, void* host, size_t bytes) {
+  Member* mm = member(c, i);
+  if (!mm) return LBSC_EINVAL;
+  return get_state_of(c, mm, host, bytes);
+}
+
+int lbsc_set_state(lbsc_ctx* c, const void* host, size_t bytes, int64_t step) {
+  Member* mm = member(c, 0);
+  if (!mm) return LBSC_EINVAL;
+  if (c->m.size() != 1) return fail(&c->err, LBSC_ESTATE, "use lbsc_member_set_state on a batch");
+  if (step < 0) return fail(&c->err, LBSC_EINVAL, "step must be >= 0");
+  const int rc = set_state_of(c, mm, host, bytes);
+  if (rc == LBSC_OK) c->step = step;
+  return rc;
+}
+
+int lbsc_member_set_state(lbsc_ctx* c, int32_t i, const void* host, size_t bytes) {
+  Member* mm = member(c, i);
+  if (!mm) return LBSC_EINVAL;
+  return set_state_of(c, mm, host, bytes);
 }
 
 int lbsc_set_tuning(lbsc_ctx* c, const lbsc_tuning* t) {
   if (!c) return LBSC_EINVAL;
   if (!t) return fail(&c->err, LBSC_EINVAL, "tuning is NULL");
-  lbsc_tuning n = default_tuning(c->p);
+  std::vector<lbsc_params> ps;
+  int nx_max = 1;
+  for (const Member& mm : c->m) {
+    ps.push_back(mm.p);
+    nx_max = std::max(nx_max, mm.p.nx);
+  }
+  lbsc_tuning n = default_tuning(ps.data(), (int32_t)ps.size());
   if (t->threads) {
     if (t->threads != 256 && t->threads != 512 && t->threads != 1024)
       return fail(&c->err, LBSC_EINVAL, "threads must be 256, 512 or 1024");
-    if (t->threads < c->p.nx)
+    if (t->threads < nx_max)
       return fail(&c->err, LBSC_EINVAL, "threads must be >= nx (full-row tiles)");
     n.threads = t->threads;
   }
@@ -335,36 +606,43 @@ int lbsc_set_tuning(lbsc_ctx* c, const lbsc_tuning* t) {
   if (t->nodes_per_thread < 0 || t->nodes_per_thread > 2)
     return fail(&c->err, LBSC_EINVAL, "nodes_per_thread must be 0, 1 or 2");
   if (t->nodes_per_thread) n.nodes_per_thread = t->nodes_per_thread;
-  if (t->block_y && (long long)t->block_y * c->p.nx > (long long)n.nodes_per_thread * n.threads)
+  if (t->block_y && (long long)t->block_y * nx_max > (long long)n.nodes_per_thread * n.threads)
     return fail(&c->err, LBSC_EINVAL, "block_y * nx exceeds nodes_per_thread * threads");
   if (t->pop_pad > kMaxPad) return fail(&c->err, LBSC_EINVAL, "pop_pad exceeds 65536");
+  if (c->batch && t->pop_pad >= 0 && t->pop_pad != kDefaultPad)
+    return fail(&c->err, LBSC_EINVAL, "a batch keeps the default population padding");
+  if (t->persistent != 0 && t->persistent != 1)
+    return fail(&c->err, LBSC_EINVAL, "persistent must be 0 or 1");
   if (t->z_chunk) n.z_chunk = t->z_chunk;
   n.block_y = t->block_y;
   n.xcd_remap = t->xcd_remap ? 1 : 0;
-  n.pop_pad = t->pop_pad;
-  const lbsc::StepArgs na = make_args(c->p, n);
-  if (na.ps != c->a.ps) {
-    // New population stride: export the state through the free lattice and
-    // import it again in the new layout.
-    hipError_t e = lbsc::launch_gather(c->p.precision, c->lat[c->cur], c->a.ps, c->lat[c->cur ^ 1],
-                                       na.ps, c->a, c->stream);
-    if (e == hipSuccess)
-      e = lbsc::launch_scatter(c->p.precision, c->lat[c->cur ^ 1], na.ps, c->lat[c->cur], na.ps,
-                               na, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "re-layout launch");
+  n.pop_pad = c->batch ? -1 : t->pop_pad;
+  n.persistent = t->persistent;
+  for (Member& mm : c->m) {
+    const lbsc::StepArgs na = make_args(mm.p, n, pad_of(n));
+    if (na.ps != mm.a.ps) {
+      // New population stride: export the state through the free lattice and
+      // import it again in the new layout.
+      hipError_t e = lbsc::launch_gather(mm.p.precision, mm.lat[c->cur], mm.a.ps,
+                                         mm.lat[c->cur ^ 1], na.ps, mm.a, c->stream);
+      if (e == hipSuccess)
+        e = lbsc::launch_scatter(mm.p.precision, mm.lat[c->cur ^ 1], na.ps, mm.lat[c->cur], na.ps,
+                                 na, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "re-layout launch");
+    }
+    mm.a = na;
   }
   c->tune = n;
-  c->a = na;
-  // The diagnostic area depends on nx, ny, nz only, not on the tuning.
-  return LBSC_OK;
+  return rebuild_tables(c);
 }
 
 int lbsc_get_tuning(const lbsc_ctx* c, lbsc_tuning* t) {
   if (!c || !t) return LBSC_EINVAL;
+  const lbsc::StepArgs& a = c->m[0].a;
   *t = c->tune;
-  t->block_y = c->a.by;
-  t->z_chunk = c->a.zchunk;
-  t->pop_pad = (int32_t)(c->a.ps - (c->a.n + 63) / 64 * 64);
+  t->block_y = a.by;
+  t->z_chunk = a.zchunk;
+  t->pop_pad = (int32_t)(a.ps - (a.n + 63) / 64 * 64);
   return LBSC_OK;
 }
 

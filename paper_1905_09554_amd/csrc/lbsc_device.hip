@@ -344,21 +344,13 @@ __device__ inline int remap_xcd(int b, int nb) {
 // previous iteration.  Four psi slots make one barrier per iteration enough:
 // the slot written at iteration k+1 was last read at iteration k-1.
 template <class T, int COLL, int FORC, int NT, int K>
-__global__ void __launch_bounds__(NT)
-k_step(const T* __restrict__ src, T* __restrict__ dst, StepArgs a) {
+__device__ inline void step_tile(const T* __restrict__ src, T* __restrict__ dst,
+                                 const StepArgs& a, int ty, int zc, T* lds) {
   using R = T;
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-  R* lds = reinterpret_cast<R*>(smem_raw);
-
   const Phys<R> ph = make_phys<R>(a);
   const int nx = a.nx, ny = a.ny, nz = a.nz, plane = a.plane;
   const long long ps = a.ps;
   const int lplane = (a.by + 2) * nx;
-
-  int b = blockIdx.x;
-  if (a.xcd_remap) b = remap_xcd(b, gridDim.x);
-  const int ty = b % a.ntiles_y;
-  const int zc = b / a.ntiles_y;
   const int y0 = ty * a.by;
   const int bye = min(a.by, ny - y0);
   const int z0 = zc * a.zchunk;
@@ -453,6 +445,90 @@ k_step(const T* __restrict__ src, T* __restrict__ dst, StepArgs a) {
     for (int k = 0; k < K; ++k)
 #pragma unroll
       for (int q = 0; q < Q; ++q) cur[k][q] = nxt[k][q];
+  }
+}
+
+// Single box: work-group b owns tile (b mod ntiles_y, b div ntiles_y).
+template <class T, int COLL, int FORC, int NT, int K>
+__global__ void __launch_bounds__(NT)
+k_step(const T* __restrict__ src, T* __restrict__ dst, StepArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  int b = blockIdx.x;
+  if (a.xcd_remap) b = remap_xcd(b, gridDim.x);
+  step_tile<T, COLL, FORC, NT, K>(src, dst, a, b % a.ntiles_y, b / a.ntiles_y,
+                                  reinterpret_cast<T*>(smem_raw));
+}
+
+// Batch of boxes (uneven sizes and parameters), one step: the tile table
+// lists (member, tile row, z chunk) for every member; work-group b runs one
+// entry.  Lattice `parity` of each member is the source.
+template <class T, int COLL, int FORC, int NT, int K>
+__global__ void __launch_bounds__(NT)
+k_step_batch(const BatchMember* __restrict__ mem, const int4* __restrict__ tiles, int parity,
+             int remap) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  int b = blockIdx.x;
+  if (remap) b = remap_xcd(b, gridDim.x);
+  const int4 t = tiles[b];
+  const StepArgs a = mem[t.x].a;
+  step_tile<T, COLL, FORC, NT, K>((const T*)mem[t.x].lat[parity], (T*)mem[t.x].lat[parity ^ 1], a,
+                                  t.y, t.z, reinterpret_cast<T*>(smem_raw));
+}
+
+// Grid-wide barrier for a cooperative launch (every work-group resident).
+// Thread 0 arrives with an agent-scope release (its group's stores become
+// visible to other XCDs) and waits with an agent-scope acquire.  The wait is
+// bounded: after spin_limit polls, or as soon as another group has recorded
+// a timeout, it records one in *err and the barrier returns false; callers
+// then leave the kernel, so every work-group reaches its end.
+__device__ inline bool grid_barrier(unsigned* count, unsigned* gen, unsigned nblocks,
+                                    unsigned* err, unsigned spin_limit) {
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ok = 1;
+    const unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned arrived =
+        __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    if (arrived == nblocks) {
+      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (++spins > spin_limit ||
+            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+          __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(8);
+      }
+    }
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+// Batch, all steps in one cooperative launch: each work-group walks the tile
+// table with stride gridDim.x, then all groups meet at a grid barrier before
+// the next step reads what this one wrote.
+template <class T, int COLL, int FORC, int NT, int K>
+__global__ void __launch_bounds__(NT)
+k_step_persistent(const BatchMember* __restrict__ mem, const int4* __restrict__ tiles,
+                  int ntiles, int parity0, int nsteps, unsigned* sync, unsigned spin_limit) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  for (int s = 0; s < nsteps; ++s) {
+    const int parity = parity0 ^ (s & 1);
+    for (int b = blockIdx.x; b < ntiles; b += gridDim.x) {
+      const int4 t = tiles[b];
+      const StepArgs a = mem[t.x].a;
+      step_tile<T, COLL, FORC, NT, K>((const T*)mem[t.x].lat[parity],
+                                      (T*)mem[t.x].lat[parity ^ 1], a, t.y, t.z,
+                                      reinterpret_cast<T*>(smem_raw));
+      __syncthreads();  // the next tile reuses the LDS ring
+    }
+    if (!grid_barrier(sync, sync + 1, gridDim.x, sync + 2, spin_limit)) return;
   }
 }
 
@@ -765,6 +841,62 @@ hipError_t launch_step(int prec, int coll, int forc, int threads, int npt, const
   if (coll == kMRT) return step_t<float, kMRT, kGuo>(threads, npt, src, dst, a, s);
   if (forc == kShift) return step_t<float, kBGK, kShift>(threads, npt, src, dst, a, s);
   return step_t<float, kBGK, kGuo>(threads, npt, src, dst, a, s);
+}
+
+template <class T, int COLL, int FORC, int NT, int K>
+static hipError_t batch_nt_k(const BatchLaunch& L, hipStream_t s) {
+  if (!L.persistent) {
+    hipLaunchKernelGGL((k_step_batch<T, COLL, FORC, NT, K>), dim3(L.ntiles), dim3(NT), L.lds, s,
+                       L.members, L.tiles, L.parity, L.remap);
+    return hipGetLastError();
+  }
+  int per_cu = 0, cus = 0, dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(&k_step_persistent<T, COLL, FORC, NT, K>), NT,
+        L.lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  int grid = per_cu * cus;
+  if (grid > L.ntiles) grid = L.ntiles;
+  const BatchMember* mem = L.members;
+  const int4* tiles = L.tiles;
+  int ntiles = L.ntiles, parity = L.parity, nsteps = L.nsteps;
+  unsigned* sync = L.sync;
+  unsigned spin = L.spin_limit;
+  void* args[] = {&mem, &tiles, &ntiles, &parity, &nsteps, &sync, &spin};
+  return hipLaunchCooperativeKernel(
+      reinterpret_cast<const void*>(&k_step_persistent<T, COLL, FORC, NT, K>), dim3(grid),
+      dim3(NT), args, (unsigned)L.lds, s);
+}
+
+template <class T, int COLL, int FORC>
+static hipError_t batch_t(const BatchLaunch& L, hipStream_t s) {
+  if (L.npt == 2) {
+    switch (L.threads) {
+      case 256: return batch_nt_k<T, COLL, FORC, 256, 2>(L, s);
+      case 512: return batch_nt_k<T, COLL, FORC, 512, 2>(L, s);
+      default: return batch_nt_k<T, COLL, FORC, 1024, 2>(L, s);
+    }
+  }
+  switch (L.threads) {
+    case 256: return batch_nt_k<T, COLL, FORC, 256, 1>(L, s);
+    case 512: return batch_nt_k<T, COLL, FORC, 512, 1>(L, s);
+    default: return batch_nt_k<T, COLL, FORC, 1024, 1>(L, s);
+  }
+}
+
+hipError_t launch_batch(const BatchLaunch& L, hipStream_t s) {
+  if (L.prec == 0) {
+    if (L.coll == kMRT) return batch_t<double, kMRT, kGuo>(L, s);
+    if (L.forc == kShift) return batch_t<double, kBGK, kShift>(L, s);
+    return batch_t<double, kBGK, kGuo>(L, s);
+  }
+  if (L.coll == kMRT) return batch_t<float, kMRT, kGuo>(L, s);
+  if (L.forc == kShift) return batch_t<float, kBGK, kShift>(L, s);
+  return batch_t<float, kBGK, kGuo>(L, s);
 }
 
 hipError_t launch_moments(int prec, const void* lat, double* rho, double* u, double* p,

@@ -22,6 +22,30 @@ struct StepArgs {
   double G, psi_rho0, tau, omega, s_bulk, s_ghost, rho_ref;
 };
 
+// One member of a batch as the device sees it: its geometry and physics and
+// its two lattices.
+struct BatchMember {
+  StepArgs a;
+  void* lat[2];
+};
+
+// A batched step: `ntiles` entries (member, tile row, z chunk, 0) in
+// `tiles`; persistent = 1 runs `nsteps` steps in one cooperative launch with
+// grid barriers (sync: 3 zeroed words), else one ordinary launch of one step.
+struct BatchLaunch {
+  int prec, coll, forc, threads, npt;
+  const BatchMember* members;
+  const int4* tiles;
+  int ntiles;
+  int parity;
+  int remap;
+  size_t lds;
+  int persistent;
+  int nsteps;
+  unsigned* sync;
+  unsigned spin_limit;
+};
+
 enum Coll { kBGK = 0, kMRT = 1 };
 enum Forc { kGuo = 0, kShift = 1 };
 
@@ -30,6 +54,7 @@ hipError_t launch_init(int prec, void* lat, const double* rho0_dev, const StepAr
                        hipStream_t s);
 hipError_t launch_step(int prec, int coll, int forc, int threads, int npt, const void* src,
                        void* dst, const StepArgs& a, hipStream_t s);
+hipError_t launch_batch(const BatchLaunch& L, hipStream_t s);
 hipError_t launch_moments(int prec, const void* lat, double* rho, double* u, double* p,
                           const StepArgs& a, hipStream_t s);
 // Diagnostics: partials holds diag_blocks(a) * 8 doubles; out holds 4 + nz.

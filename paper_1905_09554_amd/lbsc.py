@@ -49,7 +49,8 @@ class Diag(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("z_chunk", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("block_y", ctypes.c_int32),
-                ("pop_pad", ctypes.c_int32), ("nodes_per_thread", ctypes.c_int32)]
+                ("pop_pad", ctypes.c_int32), ("nodes_per_thread", ctypes.c_int32),
+                ("persistent", ctypes.c_int32)]
 
 
 class LbscError(RuntimeError):
@@ -83,6 +84,13 @@ def library():
             "lbsc_set_tuning": (ctypes.c_int, [vp, P(Tuning)]),
             "lbsc_get_tuning": (ctypes.c_int, [vp, P(Tuning)]),
             "lbsc_lattice": (None, [P(i32), P(dbl)]),
+            "lbsc_batch_state_bytes": (sz, [i32, P(Params)]),
+            "lbsc_init_batch": (ctypes.c_int, [P(vp), i32, P(Params), P(P(dbl)), vp, sz, vp]),
+            "lbsc_batch_size": (i32, [vp]),
+            "lbsc_member_moments": (ctypes.c_int, [vp, i32, vp, vp, vp]),
+            "lbsc_member_diagnostics": (ctypes.c_int, [vp, i32, dbl, dbl, P(Diag), P(dbl)]),
+            "lbsc_member_get_state": (ctypes.c_int, [vp, i32, vp, sz]),
+            "lbsc_member_set_state": (ctypes.c_int, [vp, i32, vp, sz]),
             "lbsc_destroy": (None, [vp]),
             "lbsc_last_error": (ctypes.c_char_p, [vp]),
         }
@@ -215,8 +223,8 @@ class Simulation:
 
     # -- launch shape
     def set_tuning(self, threads=0, z_chunk=0, xcd_remap=1, block_y=0, pop_pad=-1,
-                   nodes_per_thread=0):
-        t = Tuning(threads, z_chunk, xcd_remap, block_y, pop_pad, nodes_per_thread)
+                   nodes_per_thread=0, persistent=0):
+        t = Tuning(threads, z_chunk, xcd_remap, block_y, pop_pad, nodes_per_thread, persistent)
         _check(library().lbsc_set_tuning(self._ctx, ctypes.byref(t)), self._ctx)
 
     def get_tuning(self):
@@ -224,4 +232,99 @@ class Simulation:
         _check(library().lbsc_get_tuning(self._ctx, ctypes.byref(t)), self._ctx)
         return {"threads": t.threads, "z_chunk": t.z_chunk, "xcd_remap": t.xcd_remap,
                 "block_y": t.block_y, "pop_pad": t.pop_pad,
-                "nodes_per_thread": t.nodes_per_thread}
+                "nodes_per_thread": t.nodes_per_thread, "persistent": t.persistent}
+
+
+class Batch:
+    """Several periodic boxes stepped together on one GPU (one launch per
+    step, or one cooperative launch for all steps with ``persistent=1``).
+
+    rho0s: list of float64 arrays [nz, ny, nx]; params: list of Params with
+    the same precision, collision and forcing.
+    """
+
+    def __init__(self, rho0s, params, device="cuda:0", stream=None):
+        import torch
+        if len(rho0s) != len(params) or not params:
+            raise ValueError("need one rho0 per member")
+        self.params = list(params)
+        self.device = torch.device(device)
+        self._rho = [np.ascontiguousarray(r, dtype=np.float64) for r in rho0s]
+        for r, p in zip(self._rho, self.params):
+            if r.shape != (p.nz, p.ny, p.nx):
+                raise ValueError("rho0 shape %s != (nz, ny, nx)" % (r.shape,))
+        n = len(params)
+        parr = (Params * n)(*self.params)
+        nbytes = library().lbsc_batch_state_bytes(n, parr)
+        if nbytes == 0:
+            raise LbscError(LBSC_EINVAL, "invalid batch parameters")
+        self._buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._buf.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ptrs = (ctypes.POINTER(ctypes.c_double) * n)(
+            *[r.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for r in self._rho])
+        ctx = ctypes.c_void_p()
+        rc = library().lbsc_init_batch(ctypes.byref(ctx), n, parr, ptrs,
+                                       ctypes.c_void_p(base + off), nbytes,
+                                       ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != LBSC_OK:
+            msg = library().lbsc_last_error(None)
+            raise LbscError(rc, msg.decode() if msg else "")
+        self._ctx = ctx
+        self.size = n
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            library().lbsc_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, nsteps=1):
+        _check(library().lbsc_step(self._ctx, int(nsteps)), self._ctx)
+
+    @property
+    def step_count(self):
+        return int(library().lbsc_step_count(self._ctx))
+
+    def set_tuning(self, **kw):
+        Simulation.set_tuning(self, **kw)
+
+    def get_tuning(self):
+        return Simulation.get_tuning(self)
+
+    def diagnostics(self, member, rho_v, rho_l):
+        d = Diag()
+        r = np.zeros(self.params[member].nz, dtype=np.float64)
+        _check(library().lbsc_member_diagnostics(
+            self._ctx, int(member), float(rho_v), float(rho_l), ctypes.byref(d),
+            r.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self._ctx)
+        return {"mass": d.mass, "mom": [d.mom[0], d.mom[1], d.mom[2]], "r_min": d.r_min,
+                "z_argmin": d.z_argmin, "r_of_z": r}
+
+    def moments(self, member, want_u=True, want_p=False):
+        import torch
+        p = self.params[member]
+        shape = (p.nz, p.ny, p.nx)
+        rho = torch.empty(shape, dtype=torch.float64, device=self.device)
+        u = torch.empty((3,) + shape, dtype=torch.float64, device=self.device) if want_u else None
+        pr = torch.empty(shape, dtype=torch.float64, device=self.device) if want_p else None
+        _check(library().lbsc_member_moments(
+            self._ctx, int(member), ctypes.c_void_p(rho.data_ptr()),
+            ctypes.c_void_p(u.data_ptr() if u is not None else 0),
+            ctypes.c_void_p(pr.data_ptr() if pr is not None else 0)), self._ctx)
+        return rho, u, pr
+
+    def get_state(self, member):
+        p = self.params[member]
+        elem = np.float64 if p.precision == F64 else np.float32
+        out = np.empty((19, p.nz, p.ny, p.nx), dtype=elem)
+        _check(library().lbsc_member_get_state(self._ctx, int(member),
+                                               ctypes.c_void_p(out.ctypes.data), out.nbytes),
+               self._ctx)
+        return out

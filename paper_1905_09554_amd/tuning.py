@@ -31,3 +31,12 @@ def apply(sim, params):
     if t:
         sim.set_tuning(**t)
     return sim.get_tuning()
+
+
+def batch_key(workload, precision):
+    return "batch/%s/%s" % (workload, precision)
+
+
+def lookup_batch(workload, precision):
+    entry = load().get(batch_key(workload, precision))
+    return dict(entry["tuning"]) if entry else None
