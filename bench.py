@@ -145,6 +145,39 @@ def run_batch(steps, warmup):
     return out
 
 
+def run_adjoint():
+    """Adjoint of the float32 MRT step on the 64 x 64 x 256 ligament (32
+    Fourier modes), loss r_min after 4000 steps, checkpoints every 200:
+    time of the forward (with checkpoint saves) and of the backward (segment
+    recomputation plus adjoint steps)."""
+    import torch
+    import lbm_inputs
+    from paper_1905_09554_amd import lbsc
+
+    name = "adjoint_64x64x256_mrt_f32"
+    rho0, info = lbm_inputs.workload_density(name)
+    nz, ny, nx = rho0.shape
+    prm = lbsc.make_params(nx, ny, nz, collision=info["collision"], precision="f32",
+                           G=info["G"], tau=info["tau"])
+    sim = lbsc.Simulation(rho0, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.adjoint_forward(info["steps"], info["checkpoint_every"])
+    rhobar, rmin = sim.rmin_gradient(info["rho_v"], info["rho_l"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, dG, dtau = sim.adjoint_backward(rhobar)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return {"workload": name, "steps": info["steps"], "checkpoint_every": info["checkpoint_every"],
+            "forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
+            "ratio": round((t2 - t1) / (t1 - t0), 3), "r_min": rmin, "dL_dG": dG,
+            "dL_dtau": dtau}
+
+
 def cpu_baseline(rho0, info, nz_sample=16, steps=40):
     """The float64 oracle on the host: the first nz_sample planes of the same
     input as a periodic slab, `steps` steps, reported in MLUPS."""
@@ -176,6 +209,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 figure")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched sweep figure")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost figure")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the step is single-GPU; see the design notes "
@@ -200,6 +234,9 @@ def main():
     if not args.no_batch:
         batch = run_batch(max(20, args.steps // 5), 5)
         print("batch done: %.0f MLUPS" % batch["persistent"]["value"], file=sys.stderr, flush=True)
+    adj = None if args.no_adjoint else run_adjoint()
+    if adj:
+        print("adjoint done: ratio %.2f" % adj["ratio"], file=sys.stderr, flush=True)
     cpu = None if args.no_cpu_baseline else cpu_baseline(rho0, info)
 
     nz, ny, nx = rho0.shape
@@ -233,6 +270,9 @@ def main():
                         "tuning": f64["tuning"]}
     if batch:
         line["batched"] = batch
+    if adj:
+        line["adjoint_forward_cost_ratio"] = adj["ratio"]
+        line["adjoint"] = adj
     print(json.dumps(line), flush=True)
 
 

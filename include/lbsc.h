@@ -188,6 +188,43 @@ int lbsc_member_diagnostics(lbsc_ctx* c, int32_t member, double rho_v, double rh
 int lbsc_member_get_state(lbsc_ctx* c, int32_t member, void* host, size_t bytes);
 int lbsc_member_set_state(lbsc_ctx* c, int32_t member, const void* host, size_t bytes);
 
+/* ---------------------------------------------------------------- adjoint
+ * Reverse-mode gradients of a loss of the final density with respect to the
+ * initial density rho0, the interaction strength G (Eq. SC_force) and the
+ * relaxation time tau (BGK rate, or MRT shear rate 1/tau), by a hand-written
+ * adjoint of the step (Guo forcing, BGK or MRT, float64 or float32 storage;
+ * parameter gradients accumulated in float64).  Memory is held down by
+ * checkpointing: the forward saves the state every `segment` steps; the
+ * backward recomputes one segment at a time, keeping its lattices, and runs
+ * the adjoint steps through it.  Single boxes only.
+ */
+
+/* Workspace bytes for nsteps steps with checkpoints every segment steps
+ * (about (nsteps/segment + segment + 3) lattices plus segment density
+ * fields); 0 if invalid. */
+size_t lbsc_adjoint_workspace_bytes(const lbsc_params* p, int64_t nsteps, int32_t segment);
+
+/* Runs nsteps steps from the initial state (step counter 0), saving a
+ * checkpoint every `segment` steps in the caller's device workspace
+ * (borrowed until the next lbsc_adjoint_forward).  Asynchronous. */
+int lbsc_adjoint_forward(lbsc_ctx* c, int64_t nsteps, int32_t segment, void* workspace,
+                         size_t bytes);
+
+/* Loss gradient for the minimum ligament radius of the current state
+ * (Sec. 4, Fig. 5): writes dr_min/drho (N doubles, device) into rhobar_dev;
+ * *r_min receives r_min.  Nodes strictly between rho_v and rho_l on the
+ * argmin slice carry 1/(2 pi r_min (rho_l - rho_v)), all others 0.
+ * Synchronises the stream; LBSC_EINVAL if r_min = 0 (broken ligament). */
+int lbsc_rmin_gradient(lbsc_ctx* c, double rho_v, double rho_l, double* rhobar_dev,
+                       double* r_min);
+
+/* Backward pass after lbsc_adjoint_forward (the state must not have moved):
+ * rhobar_dev = dL/drho of the final state (N doubles, device); outputs
+ * dL/drho0 into rho0bar_dev (N doubles, device) and dL/dG, dL/dtau on the
+ * host.  The current state is left unchanged.  Synchronises the stream. */
+int lbsc_adjoint_backward(lbsc_ctx* c, const double* rhobar_dev, double* rho0bar_dev,
+                          double* dL_dG, double* dL_dtau);
+
 /* Overrides the launch shape of the fused step (see lbsc_tuning). */
 int lbsc_set_tuning(lbsc_ctx* c, const lbsc_tuning* t);
 int lbsc_get_tuning(const lbsc_ctx* c, lbsc_tuning* t);

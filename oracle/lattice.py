@@ -120,13 +120,11 @@ def mrt_rates(tau, s_bulk, s_ghost, s_conserved=1.0):
     (Sec. 2, MRT paragraph).  Its choice is s_bulk = 1/tau, s_ghost = 1 here;
     the conserved-row rate has no effect on the result.
     """
-    lam = [0.0] * Q
-    for r in CONSERVED_ROWS:
-        lam[r] = s_conserved
-    for r in BULK_ROWS:
-        lam[r] = s_bulk
-    for r in SHEAR_ROWS:
-        lam[r] = 1.0 / tau
-    for r in GHOST_ROWS:
-        lam[r] = s_ghost
-    return torch.tensor(lam, dtype=torch.float64)
+    lam = [None] * Q
+    for rows, val in ((CONSERVED_ROWS, s_conserved), (BULK_ROWS, s_bulk),
+                      (SHEAR_ROWS, 1.0 / tau), (GHOST_ROWS, s_ghost)):
+        for r in rows:
+            lam[r] = torch.as_tensor(val, dtype=torch.float64)
+    # torch.stack keeps autograd through tau (and the other rates) when they
+    # are tensors.
+    return torch.stack(lam)

@@ -36,6 +36,24 @@ struct Member {
   size_t lat_bytes;  // capacity of each lattice
 };
 
+// Caller workspace of the adjoint: checkpoints of the forward run, the
+// lattices and densities of one recomputed segment, the adjoint state.
+struct AdjWork {
+  bool ready = false;
+  int64_t nsteps = 0;
+  int32_t segment = 0;
+  int ncp = 0;
+  size_t lat_bytes = 0, rho_bytes = 0;
+  char* cp = nullptr;    // ncp lattices
+  char* ring = nullptr;  // segment + 1 lattices
+  char* rho = nullptr;   // segment densities
+  char* P[2] = {nullptr, nullptr};
+  char* R[2] = {nullptr, nullptr};
+  char* fbar = nullptr;  // 3 n values
+  double* partial = nullptr;
+  double* acc = nullptr;  // dL/dG, dL/dtau
+};
+
 }  // namespace
 
 struct lbsc_ctx {
@@ -54,6 +72,7 @@ struct lbsc_ctx {
   double* part;                  // diagnostic partial sums
   double* dout;                  // diagnostic results: 4 + max nz doubles
   int64_t step;
+  AdjWork adj;
   std::string err;
 };
 
@@ -150,6 +169,7 @@ lbsc::StepArgs make_args(const lbsc_params& p, const lbsc_tuning& t, long long p
   a.s_bulk = p.s_bulk;
   a.s_ghost = p.s_ghost;
   a.rho_ref = p.precision == LBSC_F64 ? 0.0 : p.rho_ref;
+  a.rho_out = nullptr;
   return a;
 }
 
@@ -477,6 +497,44 @@ int set_state_of(lbsc_ctx* c, Member* mm, const void* host, size_t bytes) {
   return LBSC_OK;
 }
 
+// Workspace layout of the adjoint for a single box (lattices sized for the
+// largest padding so any tuning of the box fits).
+struct AdjLayout {
+  size_t lat, rho, cp, ring, rhos, P, R, fbar, partial, acc, total;
+  int ncp;
+};
+
+AdjLayout adj_layout(const lbsc_params& p, int64_t nsteps, int32_t segment) {
+  AdjLayout L;
+  lbsc::StepArgs a;
+  a.n = nodes(p);
+  L.ncp = (int)((nsteps + segment - 1) / segment);
+  L.lat = lattice_bytes(p, kMaxPad);
+  L.rho = align_up((size_t)a.n * elem_size(p));
+  L.cp = (size_t)L.ncp * L.lat;
+  L.ring = (size_t)(segment + 1) * L.lat;
+  L.rhos = (size_t)segment * L.rho;
+  L.P = 2 * L.lat;
+  L.R = 2 * L.rho;
+  L.fbar = align_up(3 * (size_t)a.n * elem_size(p));
+  L.partial = align_up(2 * sizeof(double) * (size_t)lbsc::adj_blocks(a));
+  L.acc = kAlign;
+  L.total = L.cp + L.ring + L.rhos + L.P + L.R + L.fbar + L.partial + L.acc;
+  return L;
+}
+
+int check_adjoint(const lbsc_params* p, int64_t nsteps, int32_t segment, std::string* msg) {
+  int rc = check_params(p, msg);
+  if (rc != LBSC_OK) return rc;
+  if (p->forcing != LBSC_FORCING_GUO)
+    return fail(msg, LBSC_EINVAL, "the adjoint covers Guo forcing (BGK and MRT)");
+  if (nsteps < 1) return fail(msg, LBSC_EINVAL, "nsteps must be >= 1");
+  if (segment < 1 || segment > nsteps) return fail(msg, LBSC_EINVAL, "need 1 <= segment <= nsteps");
+  if ((nsteps + segment - 1) / segment > (1 << 20))
+    return fail(msg, LBSC_EINVAL, "too many checkpoints");
+  return LBSC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -643,6 +701,135 @@ int lbsc_get_tuning(const lbsc_ctx* c, lbsc_tuning* t) {
   t->block_y = a.by;
   t->z_chunk = a.zchunk;
   t->pop_pad = (int32_t)(a.ps - (a.n + 63) / 64 * 64);
+  return LBSC_OK;
+}
+
+size_t lbsc_adjoint_workspace_bytes(const lbsc_params* p, int64_t nsteps, int32_t segment) {
+  if (check_adjoint(p, nsteps, segment, nullptr) != LBSC_OK) return 0;
+  return adj_layout(*p, nsteps, segment).total;
+}
+
+int lbsc_adjoint_forward(lbsc_ctx* c, int64_t nsteps, int32_t segment, void* workspace,
+                         size_t bytes) {
+  if (!c) return LBSC_EINVAL;
+  c->adj.ready = false;
+  if (c->m.size() != 1) return fail(&c->err, LBSC_ESTATE, "the adjoint works on a single box");
+  Member& mm = c->m[0];
+  int rc = check_adjoint(&mm.p, nsteps, segment, &c->err);
+  if (rc != LBSC_OK) return rc;
+  if (c->step != 0) return fail(&c->err, LBSC_ESTATE, "the adjoint forward starts from the initial state");
+  if (!workspace || ((uintptr_t)workspace) % kAlign != 0)
+    return fail(&c->err, LBSC_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+  const AdjLayout L = adj_layout(mm.p, nsteps, segment);
+  if (bytes < L.total)
+    return fail(&c->err, LBSC_EINVAL, "workspace smaller than lbsc_adjoint_workspace_bytes");
+  AdjWork& w = c->adj;
+  char* base = (char*)workspace;
+  w.nsteps = nsteps;
+  w.segment = segment;
+  w.ncp = L.ncp;
+  w.lat_bytes = L.lat;
+  w.rho_bytes = L.rho;
+  w.cp = base;
+  base += L.cp;
+  w.ring = base;
+  base += L.ring;
+  w.rho = base;
+  base += L.rhos;
+  w.P[0] = base;
+  w.P[1] = base + L.lat;
+  base += L.P;
+  w.R[0] = base;
+  w.R[1] = base + L.rho;
+  base += L.R;
+  w.fbar = base;
+  base += L.fbar;
+  w.partial = (double*)base;
+  base += L.partial;
+  w.acc = (double*)base;
+  const size_t used = (size_t)lbsc::Q * mm.a.ps * elem_size(mm.p);
+  for (int k = 0; k < w.ncp; ++k) {
+    HIP_OR_FAIL(c, hipMemcpyAsync(w.cp + (size_t)k * w.lat_bytes, mm.lat[c->cur], used,
+                                  hipMemcpyDeviceToDevice, c->stream));
+    const int64_t len = std::min<int64_t>(segment, nsteps - (int64_t)k * segment);
+    rc = lbsc_step(c, len);
+    if (rc != LBSC_OK) return rc;
+  }
+  w.ready = true;
+  return LBSC_OK;
+}
+
+int lbsc_rmin_gradient(lbsc_ctx* c, double rho_v, double rho_l, double* rhobar_dev,
+                       double* r_min) {
+  Member* mm = member(c, 0);
+  if (!mm) return LBSC_EINVAL;
+  if (!rhobar_dev) return fail(&c->err, LBSC_EINVAL, "rhobar_dev is NULL");
+  lbsc_diag d;
+  int rc = diagnostics_of(c, mm, rho_v, rho_l, &d, nullptr);
+  if (rc != LBSC_OK) return rc;
+  if (!(d.r_min > 0)) return fail(&c->err, LBSC_EINVAL, "r_min is zero: the ligament has broken");
+  rc = moments_of(c, mm, rhobar_dev, nullptr, nullptr);
+  if (rc != LBSC_OK) return rc;
+  const double coef = 1.0 / (2.0 * 3.14159265358979323846 * d.r_min * (rho_l - rho_v));
+  HIP_OR_FAIL(c, lbsc::launch_rmin_grad(rhobar_dev, mm->a, d.z_argmin, coef, rho_v, rho_l,
+                                        c->stream));
+  if (r_min) *r_min = d.r_min;
+  return LBSC_OK;
+}
+
+int lbsc_adjoint_backward(lbsc_ctx* c, const double* rhobar_dev, double* rho0bar_dev,
+                          double* dL_dG, double* dL_dtau) {
+  if (!c) return LBSC_EINVAL;
+  AdjWork& w = c->adj;
+  if (!w.ready || c->m.size() != 1)
+    return fail(&c->err, LBSC_ESTATE, "call lbsc_adjoint_forward first");
+  if (c->step != w.nsteps)
+    return fail(&c->err, LBSC_ESTATE, "the state has moved since lbsc_adjoint_forward");
+  if (!rhobar_dev || !rho0bar_dev) return fail(&c->err, LBSC_EINVAL, "NULL gradient buffer");
+  Member& mm = c->m[0];
+  const int prec = mm.p.precision;
+  lbsc::AdjArgs g;
+  g.a = mm.a;
+  g.fbar = w.fbar;
+  g.partial = w.partial;
+  HIP_OR_FAIL(c, hipMemsetAsync(w.acc, 0, 2 * sizeof(double), c->stream));
+  int pc = 0;  // adjoint state of the step after the one being processed
+  g.p_out = w.P[pc];
+  g.r_out = w.R[pc];
+  HIP_OR_FAIL(c, lbsc::launch_adjoint_seed(prec, g, rhobar_dev, c->stream));
+  const size_t used = (size_t)lbsc::Q * mm.a.ps * elem_size(mm.p);
+  for (int seg = w.ncp - 1; seg >= 0; --seg) {
+    const int64_t len = std::min<int64_t>(w.segment, w.nsteps - (int64_t)seg * w.segment);
+    // Recompute the segment, keeping every lattice and density it uses.
+    HIP_OR_FAIL(c, hipMemcpyAsync(w.ring, w.cp + (size_t)seg * w.lat_bytes, used,
+                                  hipMemcpyDeviceToDevice, c->stream));
+    for (int64_t t = 0; t < len; ++t) {
+      lbsc::StepArgs a2 = mm.a;
+      a2.rho_out = w.rho + (size_t)t * w.rho_bytes;
+      HIP_OR_FAIL(c, lbsc::launch_step(prec, mm.p.collision, mm.p.forcing, c->tune.threads,
+                                       c->tune.nodes_per_thread,
+                                       w.ring + (size_t)t * w.lat_bytes,
+                                       w.ring + (size_t)(t + 1) * w.lat_bytes, a2, c->stream));
+    }
+    for (int64_t t = len - 1; t >= 0; --t) {
+      g.bprev = w.ring + (size_t)t * w.lat_bytes;
+      g.rho = w.rho + (size_t)t * w.rho_bytes;
+      g.p_next = w.P[pc];
+      g.r_next = w.R[pc];
+      g.p_out = w.P[pc ^ 1];
+      g.r_out = w.R[pc ^ 1];
+      HIP_OR_FAIL(c, lbsc::launch_adjoint_step(prec, mm.p.collision, g, w.acc, c->stream));
+      pc ^= 1;
+    }
+  }
+  g.p_next = w.P[pc];
+  g.r_next = w.R[pc];
+  HIP_OR_FAIL(c, lbsc::launch_adjoint_final(prec, g, rho0bar_dev, c->stream));
+  double acc[2];
+  HIP_OR_FAIL(c, hipMemcpyAsync(acc, w.acc, sizeof(acc), hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  if (dL_dG) *dL_dG = acc[0];
+  if (dL_dtau) *dL_dtau = acc[1];
   return LBSC_OK;
 }
 

@@ -433,8 +433,16 @@ __device__ inline void step_tile(const T* __restrict__ src, T* __restrict__ dst,
       const R sy = ay * R(1.0 / 18.0) + (dxy - dxmy + dyz + dymz) * R(1.0 / 36.0);
       const R sz = az * R(1.0 / 18.0) + (dxz - dxmz + dyz - dymz) * R(1.0 / 36.0);
       const R gpsi = -ph.G * pc[rc + x];
-      collide<R, COLL, FORC>(cur[k], gpsi * sx, gpsi * sy, gpsi * sz, ph);
       const unsigned idx = (unsigned)z * (unsigned)plane + (unsigned)((y0 + ly[k]) * nx + x);
+      if (a.rho_out) {
+        // The density psi was taken from (same sum order as for the LDS plane);
+        // the adjoint recomputation stores it for the force stencil.
+        R s = R(0);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) s += cur[k][q];
+        static_cast<T*>(a.rho_out)[idx] = T(ph.rho_ref + s);
+      }
+      collide<R, COLL, FORC>(cur[k], gpsi * sx, gpsi * sy, gpsi * sz, ph);
       // Written once and read only in the next step: non-temporal stores keep
       // them from evicting the rows the neighbouring tiles still re-read.
 #pragma unroll
@@ -793,6 +801,354 @@ int grid_for(long long n, int threads) {
   return (int)g;
 }
 
+// ------------------------------------------------------------------ adjoint
+// Reverse mode of one step.  Notation: B_n is the lattice written by step n
+// (post-collision values at their own node), f_n(x)_a = B_{n-1}(x - c_a)_a the
+// populations step n collides, rho_n their density.  The adjoint state between
+// steps is (P, r) with dL/dB_n(y)_a = P(y + c_a)_a + r(y + c_a):
+//   P(x)_a  adjoint of f_n(x)_a through the collision at x (incl. its
+//           dependence on the moments rho(x), j(x));
+//   r(x)    adjoint of rho_n(x) through psi, i.e. through the Shan-Chen
+//           forces at x and at its 18 neighbours.
+// Kernel A takes (P, r) of step n+1, forms dL/dB_n at every node, runs the
+// collision backwards and writes P of step n and dL/dF; kernel B turns dL/dF
+// into r of step n with the transposed force stencil.  Parameter gradients
+// (dL/dG, dL/dtau) are accumulated per block in float64.
+
+__device__ inline double block_sum2(double v0, double v1, double* out) {
+  __shared__ double red[4][2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  v0 = wave_sum(v0);
+  v1 = wave_sum(v1);
+  if (lane == 0) {
+    red[wv][0] = v0;
+    red[wv][1] = v1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+    out[1] = red[0][1] + red[1][1] + red[2][1] + red[3][1];
+  }
+  return 0.0;
+}
+
+template <class T, int COLL>
+__global__ void __launch_bounds__(256) k_adj_collide(AdjArgs g) {
+  using R = T;
+  const StepArgs& a = g.a;
+  const Phys<R> ph = make_phys<R>(a);
+  const T* __restrict__ bprev = (const T*)g.bprev;
+  const T* __restrict__ rho = (const T*)g.rho;
+  const T* __restrict__ pn = (const T*)g.p_next;
+  const T* __restrict__ rn = (const T*)g.r_next;
+  T* __restrict__ po = (T*)g.p_out;
+  T* __restrict__ fb = (T*)g.fbar;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  double dG = 0.0, dtau = 0.0;
+  if (i < a.n) {
+    const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / a.plane);
+    const Nbr nb = neighbours(x, y, z, a.nx, a.ny, a.nz, a.plane);
+    R f[Q], gb[Q];
+    pull<T, R>(bprev, a.ps, nb, f);
+    // dL/dB_n(x)_b = P(x + c_b)_b + r(x + c_b)
+    static_for<Q>([&](auto bc) {
+      constexpr int b = decltype(bc)::value;
+      const unsigned idx = nb.zo[1 + CZ[b]] + nb.yo[1 + CY[b]] + nb.xo[1 + CX[b]];
+      gb[b] = R(pn[(long long)b * a.ps + idx]) + R(rn[idx]);
+    });
+    // Shan-Chen force at x from the density field of this step.
+    R vx = R(0), vy = R(0), vz = R(0);
+    static_for<Q - 1>([&](auto bc) {
+      constexpr int b = decltype(bc)::value + 1;
+      const unsigned idx = nb.zo[1 + CZ[b]] + nb.yo[1 + CY[b]] + nb.xo[1 + CX[b]];
+      const R wp = weight<R>(b) * psi_of(R(rho[idx]), ph.psi_rho0, ph.inv_psi_rho0);
+      if constexpr (CX[b] != 0) vx += R(CX[b]) * wp;
+      if constexpr (CY[b] != 0) vy += R(CY[b]) * wp;
+      if constexpr (CZ[b] != 0) vz += R(CZ[b]) * wp;
+    });
+    const R gpsi = -ph.G * psi_of(R(rho[i]), ph.psi_rho0, ph.inv_psi_rho0);
+    const R Fx = gpsi * vx, Fy = gpsi * vy, Fz = gpsi * vz;
+    // Forward moments (as in the collision).
+    R s = R(0), jx = R(0), jy = R(0), jz = R(0);
+    static_for<Q>([&](auto ac) {
+      constexpr int q = decltype(ac)::value;
+      s += f[q];
+      if constexpr (CX[q] != 0) jx += R(CX[q]) * f[q];
+      if constexpr (CY[q] != 0) jy += R(CY[q]) * f[q];
+      if constexpr (CZ[q] != 0) jz += R(CZ[q]) * f[q];
+    });
+    const R rr = ph.rho_ref + s;
+    const R inv = R(1) / rr;
+    const R ux = (jx + R(0.5) * Fx) * inv, uy = (jy + R(0.5) * Fy) * inv,
+            uz = (jz + R(0.5) * Fz) * inv;
+    const R usq = ux * ux + uy * uy + uz * uz;
+    const R uF = ux * Fx + uy * Fy + uz * Fz;
+    // Adjoints of the collision inputs.
+    R sb = R(0), rb = R(0), ubx = R(0), uby = R(0), ubz = R(0), Fbx = R(0), Fby = R(0),
+      Fbz = R(0);
+    R pout[Q];
+    if constexpr (COLL == kBGK) {
+      const R om = ph.omega, src = R(1) - R(0.5) * om;
+      R T0 = R(0), T1x = R(0), T1y = R(0), T1z = R(0), Tcux = R(0), Tcuy = R(0), Tcuz = R(0),
+        TcFx = R(0), TcFy = R(0), TcFz = R(0), Tq = R(0), dom = R(0);
+      static_for<Q>([&](auto ac) {
+        constexpr int q = decltype(ac)::value;
+        const R w = weight<R>(q);
+        R cu = R(0), cF = R(0);
+        if constexpr (CX[q] != 0) { cu += R(CX[q]) * ux; cF += R(CX[q]) * Fx; }
+        if constexpr (CY[q] != 0) { cu += R(CY[q]) * uy; cF += R(CY[q]) * Fy; }
+        if constexpr (CZ[q] != 0) { cu += R(CZ[q]) * uz; cF += R(CZ[q]) * Fz; }
+        const R t = w * gb[q];
+        T0 += t;
+        Tq += t * (R(3) * cu + R(4.5) * cu * cu);
+        if constexpr (CX[q] != 0) { T1x += R(CX[q]) * t; Tcux += R(CX[q]) * t * cu; TcFx += R(CX[q]) * t * cF; }
+        if constexpr (CY[q] != 0) { T1y += R(CY[q]) * t; Tcuy += R(CY[q]) * t * cu; TcFy += R(CY[q]) * t * cF; }
+        if constexpr (CZ[q] != 0) { T1z += R(CZ[q]) * t; Tcuz += R(CZ[q]) * t * cu; TcFz += R(CZ[q]) * t * cF; }
+        // d f*/d omega = (f_eq - f) - S / 2
+        const R geq = w * s + w * rr * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq);
+        const R S = w * (R(3) * (cF - uF) + R(9) * cu * cF);
+        dom += gb[q] * (geq - f[q] - R(0.5) * S);
+      });
+      sb = om * T0;
+      rb = om * (Tq - R(1.5) * usq * T0);
+      ubx = om * rr * (R(3) * T1x + R(9) * Tcux - R(3) * ux * T0) + src * (R(9) * TcFx - R(3) * Fx * T0);
+      uby = om * rr * (R(3) * T1y + R(9) * Tcuy - R(3) * uy * T0) + src * (R(9) * TcFy - R(3) * Fy * T0);
+      ubz = om * rr * (R(3) * T1z + R(9) * Tcuz - R(3) * uz * T0) + src * (R(9) * TcFz - R(3) * Fz * T0);
+      Fbx = src * (R(3) * T1x - R(3) * ux * T0 + R(9) * Tcux);
+      Fby = src * (R(3) * T1y - R(3) * uy * T0 + R(9) * Tcuy);
+      Fbz = src * (R(3) * T1z - R(3) * uz * T0 + R(9) * Tcuz);
+      static_for<Q>([&](auto ac) { pout[decltype(ac)::value] = (R(1) - om) * gb[decltype(ac)::value]; });
+      dtau = -double(dom) / (double(ph.tau) * double(ph.tau));
+    } else {
+      // Moments and closed-form equilibrium / source moments as in collide().
+      const R ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
+      const R pxx = R(2) * ux2 - uy2 - uz2, pww = uy2 - uz2;
+      const R sxx = R(2) * ux * Fx - uy * Fy - uz * Fz, sww = uy * Fy - uz * Fz;
+      R meq[Q], msrc[Q];
+      static_for<Q>([&](auto ic) { meq[decltype(ic)::value] = R(0); msrc[decltype(ic)::value] = R(0); });
+      meq[1] = R(-11) * s + R(19) * rr * usq;  msrc[1] = R(38) * uF;
+      meq[2] = R(3) * s - R(5.5) * rr * usq;   msrc[2] = R(-11) * uF;
+      meq[4] = R(-2.0 / 3.0) * rr * ux;        msrc[4] = R(-2.0 / 3.0) * Fx;
+      meq[6] = R(-2.0 / 3.0) * rr * uy;        msrc[6] = R(-2.0 / 3.0) * Fy;
+      meq[8] = R(-2.0 / 3.0) * rr * uz;        msrc[8] = R(-2.0 / 3.0) * Fz;
+      meq[9] = rr * pxx;                       msrc[9] = R(2) * sxx;
+      meq[10] = R(-0.5) * rr * pxx;            msrc[10] = -sxx;
+      meq[11] = rr * pww;                      msrc[11] = R(2) * sww;
+      meq[12] = R(-0.5) * rr * pww;            msrc[12] = -sww;
+      meq[13] = rr * ux * uy;                  msrc[13] = ux * Fy + uy * Fx;
+      meq[14] = rr * uy * uz;                  msrc[14] = uy * Fz + uz * Fy;
+      meq[15] = rr * ux * uz;                  msrc[15] = ux * Fz + uz * Fx;
+      // kb_i = -sum_a M_ia gb_a; m_i = sum_b M_ib f_b
+      R mb[Q], eqb[Q], srb[Q];
+      R dlam = R(0);
+      static_for<Q>([&](auto ic) {
+        constexpr int ii = decltype(ic)::value;
+        mb[ii] = R(0);
+        eqb[ii] = R(0);
+        srb[ii] = R(0);
+        if constexpr (mrt_class(ii) != 0) {
+          R kb = R(0), m = R(0);
+          static_for<Q>([&](auto ac) {
+            constexpr int q = decltype(ac)::value;
+            if constexpr (mrt_entry(ii, q) != 0) {
+              kb -= R(mrt_entry(ii, q)) * gb[q];
+              m += R(mrt_entry(ii, q)) * f[q];
+            }
+          });
+          const R lam =
+              mrt_class(ii) == 1 ? ph.s_bulk : (mrt_class(ii) == 2 ? ph.omega : ph.s_ghost);
+          const R inv_d = R(1) / R(mrt_norm(ii));
+          mb[ii] = kb * lam * inv_d;
+          eqb[ii] = -kb * lam * inv_d;
+          srb[ii] = -kb * (R(1) - R(0.5) * lam) * inv_d;
+          if constexpr (mrt_class(ii) == 2)
+            dlam += kb * (m - meq[ii] + R(0.5) * msrc[ii]) * inv_d;
+        }
+      });
+      dtau = -double(dlam) / (double(ph.tau) * double(ph.tau));
+      // F from the conserved momentum rows (D_a += 0.1 c_a . F)
+      static_for<Q>([&](auto ac) {
+        constexpr int q = decltype(ac)::value;
+        if constexpr (CX[q] != 0) Fbx += R(0.1) * R(CX[q]) * gb[q];
+        if constexpr (CY[q] != 0) Fby += R(0.1) * R(CY[q]) * gb[q];
+        if constexpr (CZ[q] != 0) Fbz += R(0.1) * R(CZ[q]) * gb[q];
+      });
+      // Equilibrium moments back to (s, rho, u).
+      sb += R(-11) * eqb[1] + R(3) * eqb[2];
+      rb += usq * (R(19) * eqb[1] - R(5.5) * eqb[2]);
+      const R eu = rr * (R(38) * eqb[1] - R(11) * eqb[2]);
+      ubx += eu * ux;
+      uby += eu * uy;
+      ubz += eu * uz;
+      rb += R(-2.0 / 3.0) * (ux * eqb[4] + uy * eqb[6] + uz * eqb[8]);
+      ubx += R(-2.0 / 3.0) * rr * eqb[4];
+      uby += R(-2.0 / 3.0) * rr * eqb[6];
+      ubz += R(-2.0 / 3.0) * rr * eqb[8];
+      const R e9 = eqb[9] - R(0.5) * eqb[10];
+      rb += pxx * e9;
+      ubx += rr * e9 * R(4) * ux;
+      uby += rr * e9 * R(-2) * uy;
+      ubz += rr * e9 * R(-2) * uz;
+      const R e11 = eqb[11] - R(0.5) * eqb[12];
+      rb += pww * e11;
+      uby += rr * e11 * R(2) * uy;
+      ubz += rr * e11 * R(-2) * uz;
+      rb += ux * uy * eqb[13] + uy * uz * eqb[14] + ux * uz * eqb[15];
+      ubx += rr * (uy * eqb[13] + uz * eqb[15]);
+      uby += rr * (ux * eqb[13] + uz * eqb[14]);
+      ubz += rr * (uy * eqb[14] + ux * eqb[15]);
+      // Source moments back to (u, F).
+      const R e1 = R(38) * srb[1] - R(11) * srb[2];
+      ubx += e1 * Fx; uby += e1 * Fy; ubz += e1 * Fz;
+      Fbx += e1 * ux; Fby += e1 * uy; Fbz += e1 * uz;
+      Fbx += R(-2.0 / 3.0) * srb[4];
+      Fby += R(-2.0 / 3.0) * srb[6];
+      Fbz += R(-2.0 / 3.0) * srb[8];
+      const R es = R(2) * srb[9] - srb[10];
+      ubx += es * R(2) * Fx; uby -= es * Fy; ubz -= es * Fz;
+      Fbx += es * R(2) * ux; Fby -= es * uy; Fbz -= es * uz;
+      const R ew = R(2) * srb[11] - srb[12];
+      uby += ew * Fy; ubz -= ew * Fz;
+      Fby += ew * uy; Fbz -= ew * uz;
+      ubx += srb[13] * Fy + srb[15] * Fz;
+      uby += srb[13] * Fx + srb[14] * Fz;
+      ubz += srb[14] * Fy + srb[15] * Fx;
+      Fbx += srb[13] * uy + srb[15] * uz;
+      Fby += srb[13] * ux + srb[14] * uz;
+      Fbz += srb[14] * uy + srb[15] * ux;
+      // Identity part plus M^T mb.
+      static_for<Q>([&](auto ac) {
+        constexpr int q = decltype(ac)::value;
+        R acc = gb[q];
+        static_for<Q>([&](auto ic) {
+          constexpr int ii = decltype(ic)::value;
+          if constexpr (mrt_class(ii) != 0 && mrt_entry(ii, q) != 0)
+            acc += R(mrt_entry(ii, q)) * mb[ii];
+        });
+        pout[q] = acc;
+      });
+    }
+    // u = (j + F/2) / rho, rho = rho_ref + s.
+    const R jbx = ubx * inv, jby = uby * inv, jbz = ubz * inv;
+    Fbx += R(0.5) * jbx;
+    Fby += R(0.5) * jby;
+    Fbz += R(0.5) * jbz;
+    rb -= (ubx * ux + uby * uy + ubz * uz) * inv;
+    sb += rb;
+    static_for<Q>([&](auto ac) {
+      constexpr int q = decltype(ac)::value;
+      R v = pout[q] + sb;
+      if constexpr (CX[q] != 0) v += R(CX[q]) * jbx;
+      if constexpr (CY[q] != 0) v += R(CY[q]) * jby;
+      if constexpr (CZ[q] != 0) v += R(CZ[q]) * jbz;
+      po[(long long)q * a.ps + i] = T(v);
+    });
+    fb[i] = T(Fbx);
+    fb[a.n + i] = T(Fby);
+    fb[2 * a.n + i] = T(Fbz);
+    // dL/dG: F is linear in G.
+    if (a.G != 0.0)
+      dG = (double(Fbx) * double(Fx) + double(Fby) * double(Fy) + double(Fbz) * double(Fz)) / a.G;
+  }
+  block_sum2(dG, dtau, g.partial + 2LL * blockIdx.x);
+}
+
+// r(x) = psi'(rho(x)) * dL/dpsi(x), with
+// dL/dpsi(x) = -G [ Fb(x) . sum_b w_b psi(x + c_b) c_b
+//                   + sum_b w_b psi(x - c_b) Fb(x - c_b) . c_b ].
+template <class T>
+__global__ void __launch_bounds__(256) k_adj_psi(AdjArgs g) {
+  using R = T;
+  const StepArgs& a = g.a;
+  const Phys<R> ph = make_phys<R>(a);
+  const T* __restrict__ rho = (const T*)g.rho;
+  const T* __restrict__ fb = (const T*)g.fbar;
+  T* __restrict__ ro = (T*)g.r_out;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / a.plane);
+    const Nbr nb = neighbours(x, y, z, a.nx, a.ny, a.nz, a.plane);
+    R t1 = R(0), t2 = R(0);
+    const R fx = R(fb[i]), fy = R(fb[a.n + i]), fz = R(fb[2 * a.n + i]);
+    static_for<Q - 1>([&](auto bc) {
+      constexpr int b = decltype(bc)::value + 1;
+      const unsigned ip = nb.zo[1 + CZ[b]] + nb.yo[1 + CY[b]] + nb.xo[1 + CX[b]];
+      const unsigned im = nb.zo[1 - CZ[b]] + nb.yo[1 - CY[b]] + nb.xo[1 - CX[b]];
+      const R wpp = weight<R>(b) * psi_of(R(rho[ip]), ph.psi_rho0, ph.inv_psi_rho0);
+      const R wpm = weight<R>(b) * psi_of(R(rho[im]), ph.psi_rho0, ph.inv_psi_rho0);
+      R cf = R(0), cfm = R(0);
+      if constexpr (CX[b] != 0) { cf += R(CX[b]) * fx; cfm += R(CX[b]) * R(fb[im]); }
+      if constexpr (CY[b] != 0) { cf += R(CY[b]) * fy; cfm += R(CY[b]) * R(fb[a.n + im]); }
+      if constexpr (CZ[b] != 0) { cf += R(CZ[b]) * fz; cfm += R(CZ[b]) * R(fb[2 * a.n + im]); }
+      t1 += wpp * cf;
+      t2 += wpm * cfm;
+    });
+    const R r = R(rho[i]);
+    const R dpsi = (sizeof(R) == 8) ? R(exp(-double(r) * double(ph.inv_psi_rho0)))
+                                    : R(expf(-float(r) * float(ph.inv_psi_rho0)));
+    ro[i] = T(-ph.G * (t1 + t2) * dpsi);
+  }
+}
+
+// Terminal adjoint: P = 0, r = dL/drho of the final state.
+template <class T>
+__global__ void __launch_bounds__(256) k_adj_seed(AdjArgs g, const double* __restrict__ rhobar) {
+  T* __restrict__ po = (T*)g.p_out;
+  T* __restrict__ ro = (T*)g.r_out;
+  const StepArgs& a = g.a;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.n;
+       i += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) po[(long long)q * a.ps + i] = T(0);
+    ro[i] = T(rhobar[i]);
+  }
+}
+
+// dL/drho0(x) = sum_a w_a P(x)_a + r(x)  (the initial state is f_a = w_a rho0).
+template <class T>
+__global__ void __launch_bounds__(256) k_adj_final(AdjArgs g, double* __restrict__ rho0bar) {
+  const T* __restrict__ pn = (const T*)g.p_next;
+  const T* __restrict__ rn = (const T*)g.r_next;
+  const StepArgs& a = g.a;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.n;
+       i += (long long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s += weight<double>(q) * double(pn[(long long)q * a.ps + i]);
+    rho0bar[i] = s + double(rn[i]);
+  }
+}
+
+// acc[0..1] += sum of nb block partials, in a fixed order.
+__global__ void __launch_bounds__(256) k_adj_reduce(const double* __restrict__ part, int nb,
+                                                    double* __restrict__ acc) {
+  double v0 = 0.0, v1 = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) {
+    v0 += part[2LL * b];
+    v1 += part[2LL * b + 1];
+  }
+  __shared__ double tot[2];
+  block_sum2(v0, v1, tot);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    acc[0] += tot[0];
+    acc[1] += tot[1];
+  }
+}
+
+// Gradient of the minimum radius r_min = min_z sqrt(A(z)/pi) with respect to
+// rho (field given in `rho`, overwritten): only the argmin slice, and only
+// nodes strictly between rho_v and rho_l, carry 1 / (2 pi r_min (rho_l - rho_v)).
+__global__ void __launch_bounds__(256) k_rmin_grad(double* __restrict__ rho, StepArgs a, int zstar,
+                                                   double coef, double rho_v, double rho_l) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int z = (int)(i / a.plane);
+    const double r = rho[i];
+    rho[i] = (z == zstar && r > rho_v && r < rho_l) ? coef : 0.0;
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -963,6 +1319,59 @@ hipError_t launch_scatter(int prec, const void* in, long long ps_in, void* lat, 
   else
     hipLaunchKernelGGL(k_scatter<float>, dim3(g), dim3(256), 0, s, (const float*)in, ps_in,
                        (float*)lat, ps_out, a);
+  return hipGetLastError();
+}
+
+int adj_blocks(const StepArgs& a) { return (int)((a.n + 255) / 256); }
+
+hipError_t launch_adjoint_step(int prec, int coll, const AdjArgs& g, double* acc, hipStream_t s) {
+  const int nb = adj_blocks(g.a);
+  if (prec == 0) {
+    if (coll == kMRT)
+      hipLaunchKernelGGL((k_adj_collide<double, kMRT>), dim3(nb), dim3(256), 0, s, g);
+    else
+      hipLaunchKernelGGL((k_adj_collide<double, kBGK>), dim3(nb), dim3(256), 0, s, g);
+  } else {
+    if (coll == kMRT)
+      hipLaunchKernelGGL((k_adj_collide<float, kMRT>), dim3(nb), dim3(256), 0, s, g);
+    else
+      hipLaunchKernelGGL((k_adj_collide<float, kBGK>), dim3(nb), dim3(256), 0, s, g);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, s, (const double*)g.partial, nb, acc);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int gp = grid_for(g.a.n, 256);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_adj_psi<double>, dim3(gp), dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL(k_adj_psi<float>, dim3(gp), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_seed(int prec, const AdjArgs& g, const double* rhobar, hipStream_t s) {
+  const int gp = grid_for(g.a.n, 256);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_adj_seed<double>, dim3(gp), dim3(256), 0, s, g, rhobar);
+  else
+    hipLaunchKernelGGL(k_adj_seed<float>, dim3(gp), dim3(256), 0, s, g, rhobar);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_final(int prec, const AdjArgs& g, double* rho0bar, hipStream_t s) {
+  const int gp = grid_for(g.a.n, 256);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_adj_final<double>, dim3(gp), dim3(256), 0, s, g, rho0bar);
+  else
+    hipLaunchKernelGGL(k_adj_final<float>, dim3(gp), dim3(256), 0, s, g, rho0bar);
+  return hipGetLastError();
+}
+
+hipError_t launch_rmin_grad(double* rho, const StepArgs& a, int zstar, double coef, double rho_v,
+                            double rho_l, hipStream_t s) {
+  hipLaunchKernelGGL(k_rmin_grad, dim3(grid_for(a.n, 256)), dim3(256), 0, s, rho, a, zstar, coef,
+                     rho_v, rho_l);
   return hipGetLastError();
 }
 

@@ -20,6 +20,7 @@ struct StepArgs {
   int zchunk;         // planes per work-group
   int xcd_remap;      // 1: neighbouring tiles on one XCD
   double G, psi_rho0, tau, omega, s_bulk, s_ghost, rho_ref;
+  void* rho_out;      // if set, the step also writes the density it used (n values)
 };
 
 // One member of a batch as the device sees it: its geometry and physics and
@@ -46,6 +47,21 @@ struct BatchLaunch {
   unsigned spin_limit;
 };
 
+// One adjoint step (see the adjoint section of lbsc_device.hip): lattice
+// B_{n-1}, density rho_n, adjoint (P, r) of step n+1 in, of step n out,
+// dL/dF scratch (3n values) and per-block partials (2 doubles per block).
+struct AdjArgs {
+  StepArgs a;
+  const void* bprev;
+  const void* rho;
+  const void* p_next;
+  const void* r_next;
+  void* p_out;
+  void* r_out;
+  void* fbar;
+  double* partial;
+};
+
 enum Coll { kBGK = 0, kMRT = 1 };
 enum Forc { kGuo = 0, kShift = 1 };
 
@@ -68,6 +84,16 @@ hipError_t launch_gather(int prec, const void* lat, long long ps_in, void* out, 
                          const StepArgs& a, hipStream_t s);
 hipError_t launch_scatter(int prec, const void* in, long long ps_in, void* lat, long long ps_out,
                           const StepArgs& a, hipStream_t s);
+
+// Adjoint: blocks of the collision kernel (partials hold 2 doubles each);
+// one backward step (acc[0..1] += dL/dG, dL/dtau of the step); the terminal
+// seed; dL/drho0 from the adjoint of step 0; the minimum-radius gradient.
+int adj_blocks(const StepArgs& a);
+hipError_t launch_adjoint_step(int prec, int coll, const AdjArgs& g, double* acc, hipStream_t s);
+hipError_t launch_adjoint_seed(int prec, const AdjArgs& g, const double* rhobar, hipStream_t s);
+hipError_t launch_adjoint_final(int prec, const AdjArgs& g, double* rho0bar, hipStream_t s);
+hipError_t launch_rmin_grad(double* rho, const StepArgs& a, int zstar, double coef, double rho_v,
+                            double rho_l, hipStream_t s);
 
 // Velocity set and weights as the library orders them.
 void lattice_tables(int32_t* c, double* w);

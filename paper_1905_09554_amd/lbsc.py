@@ -84,6 +84,10 @@ def library():
             "lbsc_set_tuning": (ctypes.c_int, [vp, P(Tuning)]),
             "lbsc_get_tuning": (ctypes.c_int, [vp, P(Tuning)]),
             "lbsc_lattice": (None, [P(i32), P(dbl)]),
+            "lbsc_adjoint_workspace_bytes": (sz, [P(Params), i64, i32]),
+            "lbsc_adjoint_forward": (ctypes.c_int, [vp, i64, i32, vp, sz]),
+            "lbsc_rmin_gradient": (ctypes.c_int, [vp, dbl, dbl, vp, P(dbl)]),
+            "lbsc_adjoint_backward": (ctypes.c_int, [vp, vp, vp, P(dbl), P(dbl)]),
             "lbsc_batch_state_bytes": (sz, [i32, P(Params)]),
             "lbsc_init_batch": (ctypes.c_int, [P(vp), i32, P(Params), P(P(dbl)), vp, sz, vp]),
             "lbsc_batch_size": (i32, [vp]),
@@ -220,6 +224,43 @@ class Simulation:
         pops = np.ascontiguousarray(pops, dtype=self.elem)
         _check(library().lbsc_set_state(self._ctx, ctypes.c_void_p(pops.ctypes.data), pops.nbytes,
                                         int(step)), self._ctx)
+
+    # -- adjoint
+    def adjoint_forward(self, nsteps, segment):
+        """Steps nsteps from the initial state saving checkpoints every
+        `segment` steps in a device workspace owned by this object."""
+        import torch
+        nbytes = library().lbsc_adjoint_workspace_bytes(ctypes.byref(self.params), int(nsteps),
+                                                        int(segment))
+        if nbytes == 0:
+            raise LbscError(LBSC_EINVAL, "invalid adjoint request")
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._ws.data_ptr()) % 256
+        _check(library().lbsc_adjoint_forward(self._ctx, int(nsteps), int(segment),
+                                              ctypes.c_void_p(self._ws.data_ptr() + off), nbytes),
+               self._ctx)
+
+    def rmin_gradient(self, rho_v, rho_l):
+        """(dr_min/drho as a float64 device tensor [nz,ny,nx], r_min)."""
+        import torch
+        p = self.params
+        g = torch.empty((p.nz, p.ny, p.nx), dtype=torch.float64, device=self.device)
+        r = ctypes.c_double()
+        _check(library().lbsc_rmin_gradient(self._ctx, float(rho_v), float(rho_l),
+                                            ctypes.c_void_p(g.data_ptr()), ctypes.byref(r)),
+               self._ctx)
+        return g, r.value
+
+    def adjoint_backward(self, rhobar):
+        """(dL/drho0 device tensor, dL/dG, dL/dtau) for dL/drho_final = rhobar."""
+        import torch
+        rhobar = rhobar.to(device=self.device, dtype=torch.float64).contiguous()
+        out = torch.empty_like(rhobar)
+        dG, dtau = ctypes.c_double(), ctypes.c_double()
+        _check(library().lbsc_adjoint_backward(self._ctx, ctypes.c_void_p(rhobar.data_ptr()),
+                                               ctypes.c_void_p(out.data_ptr()), ctypes.byref(dG),
+                                               ctypes.byref(dtau)), self._ctx)
+        return out, dG.value, dtau.value
 
     # -- launch shape
     def set_tuning(self, threads=0, z_chunk=0, xcd_remap=1, block_y=0, pop_pad=-1,

@@ -1,0 +1,149 @@
+"""The hand-written adjoint (through the C ABI) against the oracle's autograd
+gradient and against central finite differences of the GPU forward run.
+
+Loss: minimum ligament radius after the run (Sec. 4, Fig. 5).  Gradients with
+respect to G, tau, the initial density, and through torch to the Fourier
+amplitudes of the initial radius.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs
+from oracle import adjoint as oadj
+from tests import gpu_cases as gc
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_grads(rho0, G, tau, steps, segment, coll, prec, rv, rl):
+    from paper_1905_09554_amd import lbsc
+    nz, ny, nx = rho0.shape
+    prm = lbsc.make_params(nx, ny, nz, collision=coll, precision=prec, G=G, tau=tau)
+    sim = lbsc.Simulation(rho0, prm)
+    sim.adjoint_forward(steps, segment)
+    rhobar, rmin = sim.rmin_gradient(rv, rl)
+    g_rho, g_G, g_tau = sim.adjoint_backward(rhobar)
+    out = (rmin, g_rho.cpu().numpy(), g_G, g_tau)
+    sim.close()
+    return out
+
+
+def _rmin(rho0, G, tau, steps, coll, prec, rv, rl):
+    from paper_1905_09554_amd import lbsc
+    nz, ny, nx = rho0.shape
+    prm = lbsc.make_params(nx, ny, nz, collision=coll, precision=prec, G=G, tau=tau)
+    sim = lbsc.Simulation(rho0, prm)
+    sim.step(steps)
+    r = sim.diagnostics(rv, rl)["r_min"]
+    sim.close()
+    return r
+
+
+@pytest.mark.parametrize("coll", ["bgk", "mrt"])
+def test_adjoint_matches_oracle_autograd(coll):
+    rv, rl = lbm_inputs.coexistence(-5.0)
+    rho0 = lbm_inputs.ligament_density(16, 16, 40, 4.5, 0.1, 1, rv, rl, noise=1e-3, seed=3)
+    steps, seg = 60, 16
+    rmin, g_rho, g_G, g_tau = _gpu_grads(rho0, -5.0, 0.9, steps, seg, coll, "f64", rv, rl)
+    o_rmin, o_rho, o_G, o_tau = oadj.rmin_gradients(torch.from_numpy(rho0), -5.0, 0.9, steps,
+                                                    rv, rl, collision=coll, segment=20)
+    print("%s: r_min %.6f  dG %.6e (oracle %.6e)  dtau %.6e (oracle %.6e)"
+          % (coll, rmin, g_G, o_G, g_tau, o_tau), flush=True)
+    assert abs(rmin - o_rmin) < 1e-12
+    assert abs(g_G - o_G) <= 1e-9 * abs(o_G)
+    assert abs(g_tau - o_tau) <= 1e-9 * abs(o_tau)
+    o_rho = o_rho.numpy()
+    assert float(np.abs(g_rho - o_rho).max()) <= 1e-9 * float(np.abs(o_rho).max())
+
+
+def _fourier_case(nx, ny, nz, R, nmodes, seed):
+    rv, rl = lbm_inputs.coexistence(-5.0)
+    amps = lbm_inputs.fourier_amplitudes(nmodes, R, 0.02, seed)
+    return amps, rv, rl
+
+
+def _rho_from_amps(amps, nx, ny, nz, R, rv, rl):
+    r = lbm_inputs.fourier_radius(nz, R, amps)
+    return lbm_inputs.density_from_radius(nx, ny, r, rv, rl)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-6), ("f32", 1e-4)])
+def test_adjoint_matches_central_differences(prec, tol):
+    from paper_1905_09554_amd import autograd as lag
+    nx = ny = 24
+    nz, R, steps, seg = 64, 6.0, 300, 64
+    amps, rv, rl = _fourier_case(nx, ny, nz, R, 8, seed=1)
+    cfg = dict(collision="mrt", precision=prec, steps=steps, segment=seg, rho_v=rv, rho_l=rl)
+    a = torch.tensor(amps, dtype=torch.float64, requires_grad=True)
+    G = torch.tensor(-5.0, dtype=torch.float64, requires_grad=True)
+    tau = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    r = lbm_inputs.fourier_radius_torch(nz, R, a)
+    rho0 = lbm_inputs.density_from_radius_torch(nx, ny, r, rv, rl)
+    loss = lag.ligament_rmin(rho0, G, tau, cfg)
+    loss.backward()
+    h = 1e-4
+
+    def L(am=amps, Gv=-5.0, tv=1.0):
+        # Finite differences in float64 whatever the adjoint's precision.
+        return _rmin(_rho_from_amps(am, nx, ny, nz, R, rv, rl), Gv, tv, steps, "mrt", "f64",
+                     rv, rl)
+
+    fd = {"G": (L(Gv=-5.0 + h) - L(Gv=-5.0 - h)) / (2 * h),
+          "tau": (L(tv=1.0 + h) - L(tv=1.0 - h)) / (2 * h)}
+    ad = {"G": float(G.grad), "tau": float(tau.grad)}
+    for m in (0, 1, 5):
+        e = np.zeros_like(amps)
+        e[m] = h
+        fd["a%d" % (m + 1)] = (L(am=amps + e) - L(am=amps - e)) / (2 * h)
+        ad["a%d" % (m + 1)] = float(a.grad[m])
+    for k in fd:
+        print("%s %s: adjoint %.8e  fd %.8e" % (prec, k, ad[k], fd[k]), flush=True)
+    scale = max(abs(v) for v in fd.values())
+    for k in fd:
+        assert abs(ad[k] - fd[k]) <= tol * max(abs(fd[k]), 1e-3 * scale), k
+
+
+def test_config5_full_size_adjoint_against_fd():
+    """64 x 64 x 256, R = 16, 32 Fourier modes (std 0.02 R), MRT, loss r_min
+    at step 4000, checkpoints every 200 steps.  The float32 adjoint and the
+    float64 adjoint against float64 central differences (h = 1e-4)."""
+    from paper_1905_09554_amd import autograd as lag
+    w = lbm_inputs.WORKLOADS["adjoint_64x64x256_mrt_f32"]
+    nx, ny, nz, R = w["nx"], w["ny"], w["nz"], w["R"]
+    amps, rv, rl = _fourier_case(nx, ny, nz, R, w["nmodes"], w["seed"])
+    steps, seg = w["steps"], w["checkpoint_every"]
+    res = {}
+    for prec in ("f32", "f64"):
+        cfg = dict(collision="mrt", precision=prec, steps=steps, segment=seg, rho_v=rv, rho_l=rl)
+        a = torch.tensor(amps, dtype=torch.float64, requires_grad=True)
+        G = torch.tensor(w["G"], dtype=torch.float64, requires_grad=True)
+        tau = torch.tensor(w["tau"], dtype=torch.float64, requires_grad=True)
+        rho0 = lbm_inputs.density_from_radius_torch(nx, ny, lbm_inputs.fourier_radius_torch(nz, R, a),
+                                                    rv, rl)
+        loss = lag.ligament_rmin(rho0, G, tau, cfg)
+        loss.backward()
+        res[prec] = {"r_min": float(loss.detach()), "G": float(G.grad), "tau": float(tau.grad),
+                     "a1": float(a.grad[0]), "a2": float(a.grad[1]), "a9": float(a.grad[8])}
+        print(prec, res[prec], flush=True)
+    h = 1e-4
+
+    def L(am=amps, Gv=w["G"], tv=w["tau"]):
+        return _rmin(_rho_from_amps(am, nx, ny, nz, R, rv, rl), Gv, tv, steps, "mrt", "f64", rv, rl)
+
+    fd = {"G": (L(Gv=w["G"] + h) - L(Gv=w["G"] - h)) / (2 * h),
+          "tau": (L(tv=w["tau"] + h) - L(tv=w["tau"] - h)) / (2 * h)}
+    for m in (0, 1, 8):
+        e = np.zeros_like(amps)
+        e[m] = h
+        fd["a%d" % (m + 1)] = (L(am=amps + e) - L(am=amps - e)) / (2 * h)
+    print("fd", fd, flush=True)
+    scale = max(abs(v) for v in fd.values())
+    for k in fd:
+        # float64 adjoint: exact gradient of the float64 run (FD truncation
+        # error ~1e-8); float32 adjoint: gradient of the float32 run, which
+        # differs from the float64 run by its rounding (observed <= 1.1e-4).
+        assert abs(res["f64"][k] - fd[k]) <= 1e-6 * max(abs(fd[k]), 1e-3 * scale), ("f64", k)
+        assert abs(res["f32"][k] - fd[k]) <= 5e-4 * max(abs(fd[k]), 1e-3 * scale), ("f32", k)
