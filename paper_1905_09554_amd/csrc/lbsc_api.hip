@@ -68,7 +68,7 @@ struct lbsc_ctx {
   int4* dtiles;                  // device tile table
   int ntiles;
   long long tile_cap;
-  unsigned* dsync;               // grid-barrier words (count, generation, error)
+  unsigned* dsync;               // grid-barrier words (count, generation, error, 2 tile counters)
   double* part;                  // diagnostic partial sums
   double* dout;                  // diagnostic results: 4 + max nz doubles
   int64_t step;
@@ -402,7 +402,7 @@ int step_batch(lbsc_ctx* c, int64_t nsteps) {
     L.persistent = 1;
     L.parity = c->cur;
     L.nsteps = (int)nsteps;
-    HIP_OR_FAIL(c, hipMemsetAsync(c->dsync, 0, 3 * sizeof(unsigned), c->stream));
+    HIP_OR_FAIL(c, hipMemsetAsync(c->dsync, 0, 5 * sizeof(unsigned), c->stream));
     HIP_OR_FAIL(c, lbsc::launch_batch(L, c->stream));
     unsigned flags[3];
     HIP_OR_FAIL(c, hipMemcpyAsync(flags, c->dsync, sizeof(flags), hipMemcpyDeviceToHost,
@@ -698,8 +698,13 @@ int lbsc_get_tuning(const lbsc_ctx* c, lbsc_tuning* t) {
   if (!c || !t) return LBSC_EINVAL;
   const lbsc::StepArgs& a = c->m[0].a;
   *t = c->tune;
-  t->block_y = a.by;
-  t->z_chunk = a.zchunk;
+  if (!c->batch) {
+    // A single box reports the effective rows per tile and chunk length; a
+    // batch reports what was requested (members differ), so that the result
+    // can be passed back to lbsc_set_tuning.
+    t->block_y = a.by;
+    t->z_chunk = a.zchunk;
+  }
   t->pop_pad = (int32_t)(a.ps - (a.n + 63) / 64 * 64);
   return LBSC_OK;
 }

@@ -488,9 +488,10 @@ k_step_batch(const BatchMember* __restrict__ mem, const int4* __restrict__ tiles
 // visible to other XCDs) and waits with an agent-scope acquire.  The wait is
 // bounded: after spin_limit polls, or as soon as another group has recorded
 // a timeout, it records one in *err and the barrier returns false; callers
-// then leave the kernel, so every work-group reaches its end.
+// then leave the kernel, so every work-group reaches its end.  The last group
+// to arrive also clears *reset (the tile counter of the step just finished).
 __device__ inline bool grid_barrier(unsigned* count, unsigned* gen, unsigned nblocks,
-                                    unsigned* err, unsigned spin_limit) {
+                                    unsigned* err, unsigned spin_limit, unsigned* reset) {
   __shared__ int ok;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -500,6 +501,7 @@ __device__ inline bool grid_barrier(unsigned* count, unsigned* gen, unsigned nbl
         __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
     if (arrived == nblocks) {
       __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (reset) __hip_atomic_store(reset, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       unsigned spins = 0;
@@ -518,25 +520,36 @@ __device__ inline bool grid_barrier(unsigned* count, unsigned* gen, unsigned nbl
   return ok != 0;
 }
 
-// Batch, all steps in one cooperative launch: each work-group walks the tile
-// table with stride gridDim.x, then all groups meet at a grid barrier before
-// the next step reads what this one wrote.
+// Batch, all steps in one cooperative launch.  Within a step, work-groups
+// take tiles from a shared counter (tiles differ in size across members, so
+// a dynamic queue balances them), then all groups meet at a grid barrier
+// before the next step reads what this one wrote.  Two counters alternate
+// between steps; the barrier clears the one just used.
+// sync: [0] arrivals, [1] generation, [2] timeout flag, [3..4] tile counters.
 template <class T, int COLL, int FORC, int NT, int K>
 __global__ void __launch_bounds__(NT)
 k_step_persistent(const BatchMember* __restrict__ mem, const int4* __restrict__ tiles,
                   int ntiles, int parity0, int nsteps, unsigned* sync, unsigned spin_limit) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  __shared__ int next;
   for (int s = 0; s < nsteps; ++s) {
     const int parity = parity0 ^ (s & 1);
-    for (int b = blockIdx.x; b < ntiles; b += gridDim.x) {
+    unsigned* counter = sync + 3 + (s & 1);
+    for (;;) {
+      if (threadIdx.x == 0)
+        next = (int)__hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+      const int b = next;
+      if (b >= ntiles) break;
       const int4 t = tiles[b];
       const StepArgs a = mem[t.x].a;
       step_tile<T, COLL, FORC, NT, K>((const T*)mem[t.x].lat[parity],
                                       (T*)mem[t.x].lat[parity ^ 1], a, t.y, t.z,
                                       reinterpret_cast<T*>(smem_raw));
-      __syncthreads();  // the next tile reuses the LDS ring
+      __syncthreads();  // the next tile reuses the LDS ring and `next`
     }
-    if (!grid_barrier(sync, sync + 1, gridDim.x, sync + 2, spin_limit)) return;
+    if (!grid_barrier(sync, sync + 1, gridDim.x, sync + 2, spin_limit, counter)) return;
   }
 }
 

@@ -32,7 +32,7 @@ struct BatchMember {
 
 // A batched step: `ntiles` entries (member, tile row, z chunk, 0) in
 // `tiles`; persistent = 1 runs `nsteps` steps in one cooperative launch with
-// grid barriers (sync: 3 zeroed words), else one ordinary launch of one step.
+// grid barriers (sync: 5 zeroed words), else one ordinary launch of one step.
 struct BatchLaunch {
   int prec, coll, forc, threads, npt;
   const BatchMember* members;
