@@ -155,3 +155,42 @@ def workload_density(name, seed=None):
     rho = ligament_density(w["nx"], w["ny"], w["nz"], w["R"], w["amp"], m, rho_v, rho_l,
                            noise=w["noise"], seed=w["seed"])
     return rho, dict(w, mode=m, kR_eff=kr_eff, rho_v=rho_v, rho_l=rho_l)
+
+
+# Parameters of the paper's ligament runs at G_0 = -5.3 and Oh = 0.1
+# (Sec. 3, Table 1 for SRT with velocity-shift forcing, Table 2 for MRT with
+# Guo-like forcing): box L_x x L_y x L_z with the axis along x and two
+# wavelengths of the perturbation in L_x, tau, t_cap, rho_l, rho_v, sigma.
+PAPER_G0 = -5.3
+PAPER_RADII = (14, 28, 42, 56, 70, 84, 98)
+PAPER_TABLE = {
+    "srt": {
+        "tau": (0.67926, 0.76297, 0.83053, 0.90311, 0.97021, 1.03776, 1.10647),
+        "t_cap": (335, 912, 1611, 2380, 3189, 4015, 4846),
+        "rho_l": (2.1167, 2.1254, 2.1348, 2.1450, 2.1557, 2.1666, 2.1775),
+        "rho_v": (0.0836, 0.0900, 0.0974, 0.1059, 0.1156, 0.1264, 0.1383),
+        "sigma": (0.05345, 0.05775, 0.06277, 0.06848, 0.07491, 0.08206, 0.08991),
+    },
+    "mrt": {
+        "tau": (0.67293, 0.74445, 0.79942, 0.84575, 0.88667, 0.92350, 0.95745),
+        "t_cap": (347, 981, 1803, 2775, 3878, 5098, 6424),
+        "rho_l": (2.1086, 2.1086, 2.1086, 2.1086, 2.1086, 2.1085, 2.1085),
+        "rho_v": (0.0778, 0.0779, 0.0779, 0.0779, 0.0778, 0.0778, 0.0778),
+        "sigma": (0.04951, 0.04952, 0.04952, 0.04955, 0.04953, 0.04953, 0.04954),
+    },
+}
+
+
+def paper_ligament(R0, operator, eps=0.1):
+    """Initial density and parameters of the paper's run at radius R0 (Sec. 3,
+    Tables 1-2): box L_x = 256 R0/14 along the axis (z here), L_y = L_z =
+    96 R0/14, r = R0 + eps R0 cos(4 pi z / L_x) (two wavelengths; the paper's
+    sine differs by a shift along the periodic axis), tanh wall of width 2."""
+    i = PAPER_RADII.index(R0)
+    t = PAPER_TABLE[operator]
+    lx = 256 * R0 // 14
+    ly = 96 * R0 // 14
+    rho = ligament_density(ly, ly, lx, float(R0), eps, 2, t["rho_v"][i], t["rho_l"][i])
+    return rho, {"R0": R0, "operator": operator, "eps": eps, "nx": ly, "ny": ly, "nz": lx,
+                 "G": PAPER_G0, "tau": t["tau"][i], "t_cap": t["t_cap"][i],
+                 "rho_l": t["rho_l"][i], "rho_v": t["rho_v"][i], "sigma": t["sigma"][i]}
