@@ -43,6 +43,13 @@ def coexistence(G):
     return table[key]["rho_v"], table[key]["rho_l"]
 
 
+def surface_tension(G):
+    """sigma from the oracle's Laplace test at interaction strength G."""
+    with open(os.path.join(_HERE, "coexistence.json")) as fh:
+        table = json.load(fh)
+    return table["%.4f" % G]["sigma_laplace"]["sigma"]
+
+
 def integer_mode(kR, R, nz):
     """Integer axial mode closest to kR in a periodic box of length nz."""
     m = max(1, int(round(kR * nz / (2.0 * math.pi * R))))

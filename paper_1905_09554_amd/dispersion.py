@@ -9,8 +9,11 @@ exactly one wavelength L = round(2 pi R / kR) of the perturbation
 r(z) = R (1 + A cos(2 pi z / L)).  The mode amplitude
 a(t) = (2 / L) sum_z r(z, t) cos(2 pi z / L) (with r(z) the equivalent
 radius of the interface diagnostics) grows as exp(omega t) in the linear
-stage; omega is fitted by least squares on ln a(t) over the window
-2 a(0) <= a <= 0.2 R after a 200-step relaxation of the initial tanh profile.
+stage.  A mode released from rest is the sum of the growing root and a
+decaying one of the dispersion relation, so ln a(t) reaches its asymptotic
+slope only after a few capillary times; omega is therefore fitted by least
+squares on ln a(t) over t >= 3 t_cap (t_cap = sqrt(rho_l R^3 / sigma),
+Eq. Oh_Tcap) and a <= 0.15 R, before nonlinear pinching sets in.
 """
 import math
 
@@ -23,19 +26,30 @@ from . import lbsc, tuning
 WORKLOAD = "batch64_bgk_f32"
 
 
-def make_sweep(seed=0, n=None, workload=WORKLOAD):
-    """Members of the sweep: geometry, physics and initial density."""
+def make_sweep(seed=0, n=None, workload=WORKLOAD, select=None):
+    """Members of the sweep: geometry, physics and initial density.
+
+    `select(spec) -> bool` keeps a subset of the drawn ligaments (the draw
+    itself, and so every member's geometry, does not depend on it)."""
     w = dict(lbm_inputs.WORKLOADS[workload])
     if n is not None:
         w["n"] = n
     rv, rl = lbm_inputs.coexistence(w["G"])
     members = []
     for spec in lbm_inputs.batch_ligaments(n=w["n"], seed=seed):
+        if select is not None and not select(spec):
+            continue
         rho0 = lbm_inputs.ligament_density(spec["nx"], spec["ny"], spec["nz"], spec["R"],
                                            w["amp"], 1, rv, rl)
         members.append(dict(spec, rho0=rho0, G=w["G"], tau=w["tau"], amp=w["amp"]))
-    return {"workload": workload, "seed": seed, "rho_v": rv, "rho_l": rl, "members": members,
+    return {"workload": workload, "seed": seed, "rho_v": rv, "rho_l": rl,
+            "sigma": lbm_inputs.surface_tension(w["G"]), "members": members,
             "collision": w["collision"], "precision": w["precision"]}
+
+
+def capillary_time(sweep, m):
+    """t_cap = sqrt(rho_l R^3 / sigma) of member m (Eq. Oh_Tcap)."""
+    return math.sqrt(sweep["rho_l"] * m["R"] ** 3 / sweep["sigma"])
 
 
 def member_params(sweep):
@@ -62,29 +76,23 @@ def mode_amplitude(r_of_z):
     return 2.0 / nz * float(np.sum(r_of_z * np.cos(2.0 * math.pi * z / nz)))
 
 
-def fit_growth(t, a, R, transient=200, lo_factor=2.0, hi_frac=0.2):
-    """Least-squares growth rate of ln a(t) in the linear window; None if the
-    window holds fewer than three samples (decaying or saturated modes give
-    the rate over all samples after the transient instead)."""
+def fit_growth(t, a, R, t_start, hi_frac=0.15, min_points=4):
+    """Least-squares slope of ln a(t) over t >= t_start, 0 < a <= hi_frac R;
+    None if that window holds fewer than min_points samples."""
     t = np.asarray(t, dtype=np.float64)
     a = np.asarray(a, dtype=np.float64)
-    keep = t >= transient
-    t, a = t[keep], a[keep]
-    if len(t) < 3:
-        return None
-    a0 = abs(a[0])
-    win = (np.abs(a) >= lo_factor * a0) & (np.abs(a) <= hi_frac * R) & (a > 0)
-    if win.sum() < 3:
-        win = a > 0
-    if win.sum() < 3:
+    win = (t >= t_start) & (a > 0) & (a <= hi_frac * R)
+    if win.sum() < min_points:
         return None
     slope, _ = np.polyfit(t[win], np.log(a[win]), 1)
     return float(slope)
 
 
-def run_sweep(batch, sweep, steps=3000, every=50):
+def run_sweep(batch, sweep, steps=3000, every=50, transient_tcap=3.0):
     """Steps the batch, samples every member's radius profile every `every`
-    steps, returns per-member growth rates (1 / step) and the time series."""
+    steps, returns per-member growth rates (1 / step and omega t_cap; None
+    where the run ends before the fit window holds enough samples) and the
+    time series."""
     rv, rl = sweep["rho_v"], sweep["rho_l"]
     n = len(sweep["members"])
     times, amps = [], [[] for _ in range(n)]
@@ -102,7 +110,10 @@ def run_sweep(batch, sweep, steps=3000, every=50):
         batch.step(k)
         done += k
         sample()
-    rates = [fit_growth(times, amps[i], m["R"]) for i, m in enumerate(sweep["members"])]
-    return {"t": times, "amplitude": amps, "rate": rates,
+    tcap = [capillary_time(sweep, m) for m in sweep["members"]]
+    rates = [fit_growth(times, amps[i], m["R"], transient_tcap * tcap[i])
+             for i, m in enumerate(sweep["members"])]
+    return {"t": times, "amplitude": amps, "rate": rates, "t_cap": tcap,
+            "rate_tcap": [None if r is None else r * tc for r, tc in zip(rates, tcap)],
             "kR": [m["kR_eff"] for m in sweep["members"]],
             "R": [m["R"] for m in sweep["members"]]}

@@ -8,7 +8,9 @@ Outputs
   lbm_inputs/coexistence.json   rho_v, rho_l of the flat-interface run for the
                                 interaction strengths used by the workloads
                                 (Sec. 3: flat-interface simulations provide the
-                                liquid and vapour densities).
+                                liquid and vapour densities), and sigma from
+                                the Laplace law of static cylinders (Sec. 3,
+                                the Laplace test).
 """
 import json
 import os
@@ -17,7 +19,7 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle import coexistence, lbm  # noqa: E402
+from oracle import coexistence, lbm, physics  # noqa: E402
 
 
 def flat_run(G):
@@ -34,7 +36,12 @@ def main():
     out = {}
     for G in (-5.0, -5.3):
         out["%.4f" % G] = flat_run(G)
-        print(G, out["%.4f" % G])
+        rec = out["%.4f" % G]
+        # Surface tension from the Laplace law of static cylinders (MRT).
+        sigma, icpt = physics.laplace_sigma(G, rec["rho_v"], rec["rho_l"])
+        rec["sigma_laplace"] = {"sigma": sigma, "intercept": icpt, "radii": [8, 12, 16],
+                                "box": "64x64x1", "collision": "mrt", "tau": 1.0}
+        print(G, rec)
     with open(os.path.join(ROOT, "lbm_inputs", "coexistence.json"), "w") as fh:
         json.dump(out, fh, indent=1, sort_keys=True)
         fh.write("\n")

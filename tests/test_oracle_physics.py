@@ -130,3 +130,26 @@ def test_plateau_rayleigh_growth_only_below_kR_one(nz, grows):
         assert a1 > 1.5 * a0
     else:
         assert a1 < 0.5 * a0
+
+
+def test_weber_growth_rate_limits_and_paper_value():
+    from oracle import physics
+    # Inviscid limit: (omega t_cap)^2 = x^2 (1 - x^2) / 2, maximum at x^2 = 1/2.
+    for x in (0.3, 0.5, 1 / math.sqrt(2), 0.9):
+        assert abs(physics.growth_rate_weber(x, 0.0) - math.sqrt(0.5 * x * x * (1 - x * x))) < 1e-15
+    assert physics.growth_rate_weber(1.0, 0.1) == 0.0
+    assert physics.growth_rate_weber(1.2, 0.1) == 0.0
+    # Viscosity lowers the rate.
+    assert physics.growth_rate_weber(0.7, 0.3) < physics.growth_rate_weber(0.7, 0.1)
+    # The paper's linear-stability curve (Fig. 3) uses omega t_cap = 0.2800 at
+    # kR0 ~ 0.687, Oh = 0.1 (T_break = -ln(eps) / 0.28 for all its points).
+    assert abs(physics.growth_rate_weber(0.687, 0.1) / 0.2800 - 1) < 0.04
+
+
+def test_ohnesorge_of_the_tables():
+    # Eq. Oh_Tcap with nu = (tau - 1/2)/3 gives Oh = 0.1 for Table 2's columns.
+    from oracle import physics
+    t = lbm_inputs.PAPER_TABLE["mrt"]
+    for i, R0 in enumerate(lbm_inputs.PAPER_RADII):
+        oh = physics.ohnesorge(t["tau"][i], t["rho_l"][i], t["sigma"][i], R0)
+        assert abs(oh - 0.1) < 0.002, (R0, oh)
