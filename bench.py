@@ -24,6 +24,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# What a plain float4 device copy reaches on MI355X (hand-written probe,
+# paper_1905_09554_amd/csrc/hbm_probe.hip): the practical ceiling of a
+# streaming kernel, reported beside the published peak.
+COPY_CEILING_GBS = 5350.0
 WORKLOAD = "ligament_256x256x1024_mrt_f32"
 METRIC = "MLUPS & % HBM peak, D3Q19 Shan-Chen FP32 vs FP64; adjoint/forward cost ratio"
 DIAG_EVERY = 100
@@ -66,7 +70,7 @@ def run_gpu(rho0, info, precision, steps, warmup):
     rv, rl = info["rho_v"], info["rho_l"]
 
     sim.step(warmup)
-    sim.diagnostics(rv, rl)
+    mass0 = sim.diagnostics(rv, rl)["mass"]
     torch.cuda.synchronize()
 
     # Whole-job timing: steps plus diagnostics every DIAG_EVERY steps.
@@ -110,6 +114,8 @@ def run_gpu(rho0, info, precision, steps, warmup):
         "tuning": tune,
         "r_min": diag["r_min"] if diag else None,
         "mass": diag["mass"] if diag else None,
+        # |M(end) - M(start)| / M(start) over the timed steps, per 1000 steps.
+        "mass_drift_per_1000": abs(diag["mass"] - mass0) / mass0 * 1000.0 / steps,
     }
 
 
@@ -178,6 +184,74 @@ def run_adjoint():
             "dL_dtau": dtau}
 
 
+def run_small_box(steps=1000, oracle=True):
+    """The 32 x 32 x 64 float64 BGK ligament (65 536 nodes, 20 MB of state,
+    resident in the last-level cache): the whole run of `steps` steps with
+    one launch per step and with one persistent cooperative launch, the time
+    of one isolated launch (HIP events around it: kernel plus launch latency,
+    which back-to-back launches hide), and the oracle on the same run."""
+    import torch
+    import lbm_inputs
+    from paper_1905_09554_amd import lbsc
+
+    name = "ligament_32x32x64_bgk_f64"
+    rho0, info = lbm_inputs.workload_density(name)
+    nz, ny, nx = rho0.shape
+    n = rho0.size
+    prm = lbsc.make_params(nx, ny, nz, collision="bgk", precision="f64", G=info["G"],
+                           tau=info["tau"])
+    out = {"workload": name, "nodes": n, "steps": steps, "dtype": "f64",
+           "note": "cache-resident, not HBM-bound"}
+    sim = lbsc.Simulation(rho0, prm)
+    sim.step(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(50)]
+    for e0, e1 in evs:
+        e0.record(sim.stream)
+        sim.step(1)
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+    kern = sum(e0.elapsed_time(e1) for e0, e1 in evs) / len(evs) / 1e3
+    sim.close()
+    out["per_step_launch"] = {"value": round(n * steps / wall / 1e6, 1), "unit": "MLUPS",
+                              "us_per_step": round(wall / steps * 1e6, 2)}
+    out["single_launch_us"] = round(kern * 1e6, 2)
+    b = lbsc.Batch([rho0], [prm])
+    b.set_tuning(**dict(b.get_tuning(), persistent=1))
+    b.step(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    wall_p = time.perf_counter() - t0
+    b.close()
+    torch.cuda.empty_cache()
+    out["persistent"] = {"value": round(n * steps / wall_p / 1e6, 1), "unit": "MLUPS",
+                         "us_per_step": round(wall_p / steps * 1e6, 2)}
+    if oracle:
+        from oracle import lbm
+        p = lbm.Params(G=info["G"], tau=info["tau"], collision="bgk")
+        nthreads = torch.get_num_threads()
+        res = {}
+        for threads, k in ((min(16, os.cpu_count() or 1), steps), (1, 50)):
+            torch.set_num_threads(threads)
+            f = lbm.step(lbm.init_rest(torch.from_numpy(rho0)), p)
+            t0 = time.perf_counter()
+            for _ in range(k):
+                f = lbm.step(f, p)
+            dt = time.perf_counter() - t0
+            res["threads_%d" % threads] = {"value": round(n * k / dt / 1e6, 3), "unit": "MLUPS",
+                                           "steps": k, "seconds": round(dt, 2)}
+        torch.set_num_threads(nthreads)
+        out["oracle"] = res
+    return out
+
+
 def cpu_baseline(rho0, info, nz_sample=16, steps=40):
     """The float64 oracle on the host: the first nz_sample planes of the same
     input as a periodic slab, `steps` steps, reported in MLUPS."""
@@ -210,6 +284,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched sweep figure")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost figure")
+    ap.add_argument("--no-small", action="store_true", help="skip the 32x32x64 small-box figure")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the step is single-GPU; see the design notes "
@@ -237,6 +312,12 @@ def main():
     adj = None if args.no_adjoint else run_adjoint()
     if adj:
         print("adjoint done: ratio %.2f" % adj["ratio"], file=sys.stderr, flush=True)
+    small = None
+    if not args.no_small:
+        small = run_small_box(oracle=not args.no_cpu_baseline)
+        print("small box done: %.0f MLUPS per launch, %.0f persistent"
+              % (small["per_step_launch"]["value"], small["persistent"]["value"]),
+              file=sys.stderr, flush=True)
     cpu = None if args.no_cpu_baseline else cpu_baseline(rho0, info)
 
     nz, ny, nx = rho0.shape
@@ -259,17 +340,23 @@ def main():
                    "R": info["R"], "kR_eff": round(info["kR_eff"], 4),
                    "diagnostics_every": DIAG_EVERY, "tuning": f32["tuning"]},
         "roofline": f32["roofline"],
+        "copy_ceiling": {"gbs": COPY_CEILING_GBS,
+                         "frac": round(f32["roofline"]["achieved"] / COPY_CEILING_GBS, 4)},
         "kernel_ms": round(f32["kernel_ms"], 4),
         "hbm_frac_alg": round(f32["mlups"] * 1e6 * BYTES_PER_NODE["f32"] / 1e9 / HBM_PEAK_GBS, 4),
         "cpu_baseline": cpu,
+        "mass_drift_per_1000": f32["mass_drift_per_1000"],
     }
     if f64:
         line["fp64"] = {"value": round(f64["mlups"], 1), "unit": "MLUPS", "dtype": "f64",
                         "ms_per_step": round(f64["ms_per_step"], 4),
                         "kernel_ms": round(f64["kernel_ms"], 4), "roofline": f64["roofline"],
+                        "mass_drift_per_1000": f64["mass_drift_per_1000"],
                         "tuning": f64["tuning"]}
     if batch:
         line["batched"] = batch
+    if small:
+        line["small_box"] = small
     if adj:
         line["adjoint_forward_cost_ratio"] = adj["ratio"]
         line["adjoint"] = adj

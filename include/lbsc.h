@@ -62,7 +62,7 @@ enum { LBSC_FORCING_GUO = 0, LBSC_FORCING_SHIFT = 1 };
 enum { LBSC_F64 = 0, LBSC_F32_SHIFTED = 1 };
 
 typedef struct lbsc_params {
-  int32_t nx, ny, nz;  /* periodic box, x fastest; each >= 1, nx <= 1024      */
+  int32_t nx, ny, nz;  /* periodic box, x fastest; each >= 1, nx*ny*nz < 2^31 */
   int32_t collision;   /* LBSC_BGK or LBSC_MRT                                */
   int32_t forcing;     /* LBSC_FORCING_GUO or LBSC_FORCING_SHIFT (BGK only)   */
   int32_t precision;   /* LBSC_F64 or LBSC_F32_SHIFTED                        */
@@ -84,8 +84,13 @@ typedef struct lbsc_diag {
 } lbsc_diag;
 
 /* Kernel launch shape and population layout; the autotuner picks these.
- * threads, z_chunk, block_y, nodes_per_thread: 0 means the default; pop_pad
- * < 0 means the default.  Changing pop_pad re-lays the state out in place (same values). */
+ * threads, z_chunk, block_y, nodes_per_thread, block_x: 0 means the default;
+ * pop_pad < 0 means the default.  A tile of the fused step is block_x columns
+ * by block_y rows (block_x * block_y <= nodes_per_thread * threads); the
+ * default block_x is the whole row when the work-group holds two or more
+ * rows and 2 nx <= threads, else the widest multiple of 64 whose tile and
+ * halo ring (2 (block_x + 2) + 2 block_y nodes) fit the work-group.  Changing pop_pad re-lays the state out in
+ * place (same values). */
 typedef struct lbsc_tuning {
   int32_t threads;     /* work-group size of the fused step: 256, 512, 1024   */
   int32_t z_chunk;     /* planes marched per work-group (>= 1)                */
@@ -95,6 +100,7 @@ typedef struct lbsc_tuning {
   int32_t nodes_per_thread; /* interior nodes each thread carries: 1 or 2      */
   int32_t persistent;  /* 1: all steps of one lbsc_step call in one cooperative
                           launch with grid barriers; 0: one launch per step   */
+  int32_t block_x;     /* columns per tile; 0 = the default above             */
 } lbsc_tuning;
 
 /* Bytes of device memory a context with these parameters needs: two

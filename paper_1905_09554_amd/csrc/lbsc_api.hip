@@ -87,6 +87,9 @@ constexpr long long kMaxPad = 65536;
 constexpr long long kDefaultPad = 1088;
 // Polls of a grid barrier before it reports a timeout (about a second).
 constexpr unsigned kSpinLimit = 1u << 23;
+// Narrowest tile that does not span a whole row (one wavefront of columns);
+// bounds the size of the tile table.
+constexpr int kMinBlockX = 64;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 size_t elem_size(const lbsc_params& p) { return p.precision == LBSC_F64 ? 8 : 4; }
@@ -102,7 +105,6 @@ int check_params(const lbsc_params* p, std::string* msg) {
   if (!p) return fail(msg, LBSC_EINVAL, "params is NULL");
   if (p->nx < 1 || p->ny < 1 || p->nz < 1)
     return fail(msg, LBSC_EINVAL, "box dimensions must be >= 1");
-  if (p->nx > 1024) return fail(msg, LBSC_EINVAL, "nx > 1024 is not supported (full-row tiles)");
   if (nodes(*p) > 0x7fffffffLL) return fail(msg, LBSC_EINVAL, "more than 2^31 - 1 nodes");
   if (p->collision != LBSC_BGK && p->collision != LBSC_MRT)
     return fail(msg, LBSC_EINVAL, "collision must be LBSC_BGK or LBSC_MRT");
@@ -143,6 +145,36 @@ int check_batch(int32_t n, const lbsc_params* p, std::string* msg) {
   return LBSC_OK;
 }
 
+// Tile of the fused step: bx columns by by rows, at most cap = npt * threads
+// nodes.  Each plane of the z-march also reloads the tile's halo ring, one
+// node per thread; a ring larger than the work-group costs a second round of
+// dependent loads.  Default bx: whole rows when the group holds two or more
+// of them and their two halo rows fit one round (2 nx <= threads); else the
+// widest multiple of 64 columns whose ring, 2 (bx + 2) + 2 by, fits one
+// round with by = cap / bx >= 2 rows.  Four psi planes of (by + 2)(bx + 2)
+// values must fit the 160 KB of LDS of a CU.
+int default_block_x(int nx, long long cap, int threads) {
+  if (2LL * nx <= cap && 2LL * nx <= threads) return nx;
+  for (long long bx = std::min<long long>(nx, cap / 2) / 64 * 64; bx >= 64; bx -= 64)
+    if (2 * (bx + 2) + 2 * (cap / bx) <= threads) return (int)bx;
+  return std::min<int>(nx, 64);
+}
+
+void tile_shape(int nx, int ny, long long cap, int threads, int block_x, int block_y, size_t elem,
+                int* bx_out, int* by_out) {
+  int bx = block_x > 0 ? block_x : default_block_x(nx, cap, threads);
+  if (bx > nx) bx = nx;
+  if (bx > cap) bx = (int)cap;
+  const int rows = (int)std::max(1LL, cap / bx);
+  int by = block_y > 0 ? block_y : rows;
+  if (by > rows) by = rows;
+  if (by < 1) by = 1;
+  if (by > ny) by = ny;
+  while (by > 1 && 4LL * (by + 2) * (bx + 2) * (long long)elem > 160 * 1024) --by;
+  *bx_out = bx;
+  *by_out = by;
+}
+
 lbsc::StepArgs make_args(const lbsc_params& p, const lbsc_tuning& t, long long pad) {
   lbsc::StepArgs a;
   a.nx = p.nx;
@@ -151,15 +183,10 @@ lbsc::StepArgs make_args(const lbsc_params& p, const lbsc_tuning& t, long long p
   a.plane = p.nx * p.ny;
   a.n = nodes(p);
   a.ps = (a.n + 63) / 64 * 64 + pad;
-  const int rows = t.nodes_per_thread * t.threads / p.nx;  // rows the group can hold
-  int by = t.block_y > 0 ? t.block_y : rows;
-  if (by > rows) by = rows;
-  if (by < 1) by = 1;
-  if (by > p.ny) by = p.ny;
-  // Four psi planes of (by + 2) rows must fit the 160 KB of LDS of a CU.
-  while (by > 1 && 4LL * (by + 2) * p.nx * (long long)elem_size(p) > 160 * 1024) --by;
-  a.by = by;
-  a.ntiles_y = (p.ny + by - 1) / by;
+  tile_shape(p.nx, p.ny, (long long)t.nodes_per_thread * t.threads, t.threads, t.block_x,
+             t.block_y, elem_size(p), &a.bx, &a.by);
+  a.ntiles_x = (p.nx + a.bx - 1) / a.bx;
+  a.ntiles_y = (p.ny + a.by - 1) / a.by;
   a.zchunk = t.z_chunk > 0 ? (t.z_chunk > p.nz ? p.nz : t.z_chunk) : p.nz;
   a.xcd_remap = t.xcd_remap;
   a.G = p.G;
@@ -176,28 +203,27 @@ lbsc::StepArgs make_args(const lbsc_params& p, const lbsc_tuning& t, long long p
 long long pad_of(const lbsc_tuning& t) { return t.pop_pad >= 0 ? t.pop_pad : kDefaultPad; }
 
 lbsc_tuning default_tuning(const lbsc_params* p, int32_t n) {
-  int nx = 1, ny = 1;
-  long long work = 0;
-  for (int32_t i = 0; i < n; ++i) {
-    nx = std::max(nx, p[i].nx);
-    ny = std::max(ny, p[i].ny);
-    work += (long long)p[i].ny * p[i].nz;
-  }
   lbsc_tuning t;
   // Two or more work-groups per CU overlap one group's loads with another's
   // collision; float64 needs twice the registers, so smaller groups.
   t.threads = p[0].precision == LBSC_F64 ? 256 : 512;
-  while (t.threads < nx) t.threads *= 2;
+  t.block_x = 0;
   t.block_y = 0;
   t.xcd_remap = 1;
   t.pop_pad = -1;
   t.nodes_per_thread = 1;
   t.persistent = 0;
-  // Enough work-groups to fill 256 CUs a few times over, but long z-marches
-  // so the two extra halo planes of each chunk stay a small fraction.
-  const int by = std::max(1, std::min(ny, t.threads / nx));
-  long long zc = (work / by + 2047) / 2048;
-  if (zc < 8) zc = 8;
+  // About two work-groups per CU (512 in all): long z-marches keep the two
+  // extra halo planes of each chunk a small fraction on large boxes, short
+  // ones give small boxes enough groups.
+  long long columns = 0;  // xy tiles times planes, over all members
+  for (int32_t i = 0; i < n; ++i) {
+    int bx = 1, by = 1;
+    tile_shape(p[i].nx, p[i].ny, t.threads, t.threads, 0, 0, elem_size(p[i]), &bx, &by);
+    columns += (long long)((p[i].nx + bx - 1) / bx) * ((p[i].ny + by - 1) / by) * p[i].nz;
+  }
+  long long zc = (columns + 511) / 512;
+  if (zc < 1) zc = 1;
   if (zc > 64) zc = 64;
   t.z_chunk = (int)zc;
   return t;
@@ -207,8 +233,8 @@ size_t lattice_bytes(const lbsc_params& p, long long pad) {
   return align_up((size_t)lbsc::Q * (size_t)((nodes(p) + 63) / 64 * 64 + pad) * elem_size(p));
 }
 
-// Sizes of the aux area (tile capacity: one tile per row and plane, the
-// finest possible tiling).
+// Sizes of the aux area (tile capacity: the finest tiling allowed, one row of
+// min(nx, kMinBlockX) columns per plane).
 struct AuxSizes {
   size_t members, tiles, sync, part, out, total;
   long long tile_cap;
@@ -219,7 +245,8 @@ AuxSizes aux_sizes(int32_t n, const lbsc_params* p) {
   long long cap = 0;
   int max_blocks = 0, max_nz = 0;
   for (int32_t i = 0; i < n; ++i) {
-    cap += (long long)p[i].ny * p[i].nz;
+    const int bmin = std::min(p[i].nx, kMinBlockX);
+    cap += (long long)p[i].ny * p[i].nz * ((p[i].nx + bmin - 1) / bmin);
     lbsc::StepArgs a;
     a.plane = p[i].nx * p[i].ny;
     a.nz = p[i].nz;
@@ -264,8 +291,9 @@ int rebuild_tables(lbsc_ctx* c) {
     hm[i].lat[0] = c->m[i].lat[0];
     hm[i].lat[1] = c->m[i].lat[1];
     const int nchunks = (a.nz + a.zchunk - 1) / a.zchunk;
+    const int ntxy = a.ntiles_x * a.ntiles_y;
     for (int zc = 0; zc < nchunks; ++zc)
-      for (int ty = 0; ty < a.ntiles_y; ++ty) ht.push_back(make_int4((int)i, ty, zc, 0));
+      for (int t = 0; t < ntxy; ++t) ht.push_back(make_int4((int)i, t, zc, 0));
   }
   if ((long long)ht.size() > c->tile_cap)
     return fail(&c->err, LBSC_EINVAL, "tile table exceeds its capacity");
@@ -394,7 +422,7 @@ int step_batch(lbsc_ctx* c, int64_t nsteps) {
   L.remap = c->tune.xcd_remap;
   L.lds = 0;
   for (const Member& mm : c->m)
-    L.lds = std::max(L.lds, (size_t)4 * (mm.a.by + 2) * mm.a.nx * elem_size(mm.p));
+    L.lds = std::max(L.lds, (size_t)4 * (mm.a.by + 2) * (mm.a.bx + 2) * elem_size(mm.p));
   L.sync = c->dsync;
   L.spin_limit = kSpinLimit;
   if (c->tune.persistent) {
@@ -656,16 +684,20 @@ int lbsc_set_tuning(lbsc_ctx* c, const lbsc_tuning* t) {
   if (t->threads) {
     if (t->threads != 256 && t->threads != 512 && t->threads != 1024)
       return fail(&c->err, LBSC_EINVAL, "threads must be 256, 512 or 1024");
-    if (t->threads < nx_max)
-      return fail(&c->err, LBSC_EINVAL, "threads must be >= nx (full-row tiles)");
     n.threads = t->threads;
   }
-  if (t->z_chunk < 0 || t->block_y < 0) return fail(&c->err, LBSC_EINVAL, "negative tuning value");
+  if (t->z_chunk < 0 || t->block_y < 0 || t->block_x < 0)
+    return fail(&c->err, LBSC_EINVAL, "negative tuning value");
   if (t->nodes_per_thread < 0 || t->nodes_per_thread > 2)
     return fail(&c->err, LBSC_EINVAL, "nodes_per_thread must be 0, 1 or 2");
   if (t->nodes_per_thread) n.nodes_per_thread = t->nodes_per_thread;
-  if (t->block_y && (long long)t->block_y * nx_max > (long long)n.nodes_per_thread * n.threads)
-    return fail(&c->err, LBSC_EINVAL, "block_y * nx exceeds nodes_per_thread * threads");
+  const long long cap = (long long)n.nodes_per_thread * n.threads;
+  if (t->block_x > 0 && t->block_x < kMinBlockX && t->block_x < nx_max)
+    return fail(&c->err, LBSC_EINVAL, "block_x must be 0, >= 64 or >= nx");
+  if (t->block_x > cap)
+    return fail(&c->err, LBSC_EINVAL, "block_x exceeds nodes_per_thread * threads");
+  if (t->block_y && (long long)t->block_y * std::max(1, t->block_x) > cap)
+    return fail(&c->err, LBSC_EINVAL, "block_x * block_y exceeds nodes_per_thread * threads");
   if (t->pop_pad > kMaxPad) return fail(&c->err, LBSC_EINVAL, "pop_pad exceeds 65536");
   if (c->batch && t->pop_pad >= 0 && t->pop_pad != kDefaultPad)
     return fail(&c->err, LBSC_EINVAL, "a batch keeps the default population padding");
@@ -673,6 +705,7 @@ int lbsc_set_tuning(lbsc_ctx* c, const lbsc_tuning* t) {
     return fail(&c->err, LBSC_EINVAL, "persistent must be 0 or 1");
   if (t->z_chunk) n.z_chunk = t->z_chunk;
   n.block_y = t->block_y;
+  n.block_x = t->block_x;
   n.xcd_remap = t->xcd_remap ? 1 : 0;
   n.pop_pad = c->batch ? -1 : t->pop_pad;
   n.persistent = t->persistent;
@@ -702,6 +735,7 @@ int lbsc_get_tuning(const lbsc_ctx* c, lbsc_tuning* t) {
     // A single box reports the effective rows per tile and chunk length; a
     // batch reports what was requested (members differ), so that the result
     // can be passed back to lbsc_set_tuning.
+    t->block_x = a.bx;
     t->block_y = a.by;
     t->z_chunk = a.zchunk;
   }

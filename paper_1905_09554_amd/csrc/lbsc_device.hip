@@ -336,22 +336,29 @@ __device__ inline int remap_xcd(int b, int nb) {
 }
 
 // ---------------------------------------------------------------- the step
-// One work-group of NT threads owns rows [y0, y0 + by) (by <= K NT / nx) of
-// all x and planes [z0, z1); each thread carries K interior nodes (tile
-// indices tid + k NT).  Iteration of plane z: pull plane z+1 (tile and both
-// halo rows), publish psi(z+1) to LDS slot (k+2)%4, barrier, then force and
-// collision of plane z from the populations kept in registers since the
-// previous iteration.  Four psi slots make one barrier per iteration enough:
-// the slot written at iteration k+1 was last read at iteration k-1.
+// One work-group of NT threads owns the tile of columns [x0, x0 + bx) and
+// rows [y0, y0 + by) (bx * by <= K NT) over planes [z0, z1); each thread
+// carries K interior nodes (tile indices tid + k NT).  Iteration of plane z:
+// pull plane z+1 (tile plus its one-node ring of halo nodes), publish
+// psi(z+1) to LDS slot (k+2)%4, barrier, then force and collision of plane z
+// from the populations kept in registers since the previous iteration.  Four
+// psi slots make one barrier per iteration enough: the slot written at
+// iteration k+1 was last read at iteration k-1.  An LDS psi plane is
+// (by + 2) rows of (bx + 2) values; the halo ring is recomputed from its own
+// 19 pulled loads (mostly cache hits: they are the neighbouring tiles'
+// interior).
 template <class T, int COLL, int FORC, int NT, int K>
 __device__ inline void step_tile(const T* __restrict__ src, T* __restrict__ dst,
-                                 const StepArgs& a, int ty, int zc, T* lds) {
+                                 const StepArgs& a, int txy, int zc, T* lds) {
   using R = T;
   const Phys<R> ph = make_phys<R>(a);
   const int nx = a.nx, ny = a.ny, nz = a.nz, plane = a.plane;
   const long long ps = a.ps;
-  const int lplane = (a.by + 2) * nx;
-  const int y0 = ty * a.by;
+  const int lw = a.bx + 2;
+  const int lplane = (a.by + 2) * lw;
+  const int tx = txy % a.ntiles_x, ty = txy / a.ntiles_x;
+  const int x0 = tx * a.bx, y0 = ty * a.by;
+  const int bxe = min(a.bx, nx - x0);
   const int bye = min(a.by, ny - y0);
   const int z0 = zc * a.zchunk;
   const int z1 = min(nz, z0 + a.zchunk);
@@ -362,22 +369,28 @@ __device__ inline void step_tile(const T* __restrict__ src, T* __restrict__ dst,
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int i = tid + k * NT;
-    lx[k] = i % nx;
-    ly[k] = i / nx;
-    interior[k] = ly[k] < bye;
+    lx[k] = i % a.bx;
+    ly[k] = i / a.bx;
+    interior[k] = ly[k] < bye && lx[k] < bxe;
   }
-  const int nhalo = 2 * nx;
+  // Halo ring: rows -1 and bye over columns -1..bxe, then columns -1 and bxe
+  // over rows 0..bye-1.  A tile of whole rows has no halo columns of its own:
+  // columns -1 and bxe are the row's last and first node, which the owners of
+  // those nodes store a second time.
+  const bool whole_rows = bxe == nx;
+  const int hrow = whole_rows ? bxe : bxe + 2;
+  const int nhalo = whole_rows ? 2 * bxe : 2 * hrow + 2 * bye;
 
   R cur[K][Q], nxt[K][Q];
 
-  // Pulls plane z: psi of the tile plus both halo rows into LDS slot `slot`;
+  // Pulls plane z: psi of the tile plus its halo ring into LDS slot `slot`;
   // interior populations into `keep`.
   auto load_plane = [&](int z, int slot, R(&keep)[K][Q]) {
     R* lp = lds + slot * lplane;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (interior[k]) {
-        const Nbr nb = neighbours(lx[k], y0 + ly[k], z, nx, ny, nz, plane);
+        const Nbr nb = neighbours(x0 + lx[k], y0 + ly[k], z, nx, ny, nz, plane);
         pull<T, R>(src, ps, nb, keep[k]);
       }
     }
@@ -387,17 +400,35 @@ __device__ inline void step_tile(const T* __restrict__ src, T* __restrict__ dst,
         R s = R(0);
 #pragma unroll
         for (int q = 0; q < Q; ++q) s += keep[k][q];
-        lp[(ly[k] + 1) * nx + lx[k]] = psi_of(ph.rho_ref + s, ph.psi_rho0, ph.inv_psi_rho0);
+        const R v = psi_of(ph.rho_ref + s, ph.psi_rho0, ph.inv_psi_rho0);
+        R* row = lp + (ly[k] + 1) * lw;
+        row[lx[k] + 1] = v;
+        if (whole_rows && lx[k] == 0) row[bxe + 1] = v;
+        if (whole_rows && lx[k] == bxe - 1) row[0] = v;
       }
     }
     for (int h = tid; h < nhalo; h += NT) {
-      const int hl = h < nx ? -1 : bye;
-      const int hx = h < nx ? h : h - nx;
-      int hy = y0 + hl;
+      int hl, hc;
+      if (whole_rows) {
+        hl = h < bxe ? -1 : bye;
+        hc = h < bxe ? h : h - bxe;
+      } else if (h < 2 * hrow) {
+        hl = h < hrow ? -1 : bye;
+        hc = (h < hrow ? h : h - hrow) - 1;
+      } else {
+        const int g = h - 2 * hrow;
+        hc = g < bye ? -1 : bxe;
+        hl = g < bye ? g : g - bye;
+      }
+      int hy = y0 + hl, hx = x0 + hc;
       hy = hy < 0 ? hy + ny : (hy >= ny ? hy - ny : hy);
+      hx = hx < 0 ? hx + nx : (hx >= nx ? hx - nx : hx);
       const Nbr nb = neighbours(hx, hy, z, nx, ny, nz, plane);
-      const R s = pull_sum<T, R>(src, ps, nb);
-      lp[(hl + 1) * nx + hx] = psi_of(ph.rho_ref + s, ph.psi_rho0, ph.inv_psi_rho0);
+      const R v = psi_of(ph.rho_ref + pull_sum<T, R>(src, ps, nb), ph.psi_rho0, ph.inv_psi_rho0);
+      R* row = lp + (hl + 1) * lw;
+      row[hc + 1] = v;
+      if (whole_rows && hc == 0) row[bxe + 1] = v;
+      if (whole_rows && hc == bxe - 1) row[0] = v;
     }
   };
 
@@ -415,10 +446,9 @@ __device__ inline void step_tile(const T* __restrict__ src, T* __restrict__ dst,
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (!interior[k]) continue;
-      const int x = lx[k];
-      const int xm = x == 0 ? nx - 1 : x - 1;
-      const int xp = x == nx - 1 ? 0 : x + 1;
-      const int rm = ly[k] * nx, rc = (ly[k] + 1) * nx, rp = (ly[k] + 2) * nx;
+      const int x = lx[k] + 1;  // LDS column; x - 1 and x + 1 are in the ring
+      const int xm = x - 1, xp = x + 1;
+      const int rm = ly[k] * lw, rc = (ly[k] + 1) * lw, rp = (ly[k] + 2) * lw;
       // sum_a w_a psi(x + c_a) c_a, axis links weight 1/18, diagonals 1/36.
       const R ax = pc[rc + xp] - pc[rc + xm];
       const R ay = pc[rp + x] - pc[rm + x];
@@ -433,7 +463,8 @@ __device__ inline void step_tile(const T* __restrict__ src, T* __restrict__ dst,
       const R sy = ay * R(1.0 / 18.0) + (dxy - dxmy + dyz + dymz) * R(1.0 / 36.0);
       const R sz = az * R(1.0 / 18.0) + (dxz - dxmz + dyz - dymz) * R(1.0 / 36.0);
       const R gpsi = -ph.G * pc[rc + x];
-      const unsigned idx = (unsigned)z * (unsigned)plane + (unsigned)((y0 + ly[k]) * nx + x);
+      const unsigned idx =
+          (unsigned)z * (unsigned)plane + (unsigned)((y0 + ly[k]) * nx + x0 + lx[k]);
       if (a.rho_out) {
         // The density psi was taken from (same sum order as for the LDS plane);
         // the adjoint recomputation stores it for the force stencil.
@@ -456,19 +487,21 @@ __device__ inline void step_tile(const T* __restrict__ src, T* __restrict__ dst,
   }
 }
 
-// Single box: work-group b owns tile (b mod ntiles_y, b div ntiles_y).
+// Single box: work-group b owns xy tile b mod (ntiles_x ntiles_y) of z chunk
+// b div (ntiles_x ntiles_y).
 template <class T, int COLL, int FORC, int NT, int K>
 __global__ void __launch_bounds__(NT)
 k_step(const T* __restrict__ src, T* __restrict__ dst, StepArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   int b = blockIdx.x;
   if (a.xcd_remap) b = remap_xcd(b, gridDim.x);
-  step_tile<T, COLL, FORC, NT, K>(src, dst, a, b % a.ntiles_y, b / a.ntiles_y,
+  const int ntxy = a.ntiles_x * a.ntiles_y;
+  step_tile<T, COLL, FORC, NT, K>(src, dst, a, b % ntxy, b / ntxy,
                                   reinterpret_cast<T*>(smem_raw));
 }
 
 // Batch of boxes (uneven sizes and parameters), one step: the tile table
-// lists (member, tile row, z chunk) for every member; work-group b runs one
+// lists (member, xy tile, z chunk) for every member; work-group b runs one
 // entry.  Lattice `parity` of each member is the source.
 template <class T, int COLL, int FORC, int NT, int K>
 __global__ void __launch_bounds__(NT)
@@ -1187,9 +1220,9 @@ static void step_nt(int npt, int grid, size_t lds, const T* in, T* out, const St
 template <class T, int COLL, int FORC>
 static hipError_t step_t(int threads, int npt, const void* src, void* dst, const StepArgs& a,
                          hipStream_t s) {
-  const int grid = a.ntiles_y * ((a.nz + a.zchunk - 1) / a.zchunk);
-  const size_t lds = (size_t)4 * (a.by + 2) * a.nx * sizeof(T);
-  if ((long long)a.by * a.nx > (long long)npt * threads) return hipErrorInvalidValue;
+  const int grid = a.ntiles_x * a.ntiles_y * ((a.nz + a.zchunk - 1) / a.zchunk);
+  const size_t lds = (size_t)4 * (a.by + 2) * (a.bx + 2) * sizeof(T);
+  if ((long long)a.by * a.bx > (long long)npt * threads) return hipErrorInvalidValue;
   const T* in = (const T*)src;
   T* out = (T*)dst;
   switch (threads) {

@@ -15,7 +15,9 @@ struct StepArgs {
   int plane;          // nx * ny
   long long n;        // nodes
   long long ps;       // stride between populations (elements), >= n
+  int bx;             // columns per tile
   int by;             // rows per tile
+  int ntiles_x;       // ceil(nx / bx)
   int ntiles_y;       // ceil(ny / by)
   int zchunk;         // planes per work-group
   int xcd_remap;      // 1: neighbouring tiles on one XCD
@@ -30,7 +32,7 @@ struct BatchMember {
   void* lat[2];
 };
 
-// A batched step: `ntiles` entries (member, tile row, z chunk, 0) in
+// A batched step: `ntiles` entries (member, xy tile, z chunk, 0) in
 // `tiles`; persistent = 1 runs `nsteps` steps in one cooperative launch with
 // grid barriers (sync: 5 zeroed words), else one ordinary launch of one step.
 struct BatchLaunch {

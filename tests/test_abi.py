@@ -43,7 +43,7 @@ def _params(**kw):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(nx=0), dict(ny=-1), dict(nx=2048), dict(tau=0.5), dict(tau=float("nan")),
+    dict(nx=0), dict(ny=-1), dict(nx=2048, ny=1024, nz=1024), dict(tau=0.5), dict(tau=float("nan")),
     dict(G=float("inf")), dict(psi_rho0=0.0), dict(collision="mrt", s_ghost=2.0),
     dict(collision="mrt", s_bulk=0.0), dict(collision="mrt", forcing="shift"),
 ])
@@ -58,6 +58,8 @@ def test_state_size_counts_two_lattices():
         assert lbsc.state_bytes(p) >= 2 * 19 * n * size
         # plus room for up to 65536 padding elements between population arrays
         assert lbsc.state_bytes(p) < 2 * 19 * (n + 64 + 65536) * size + 64 * 1024
+    # nx beyond one work-group: tiles split rows (no nx limit of its own)
+    assert lbsc.state_bytes(_params(nx=4096, ny=2, nz=2)) > 0
 
 
 def _init(params, rho0, buf=0x10000000, nbytes=None):

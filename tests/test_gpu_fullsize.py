@@ -15,10 +15,10 @@ pytestmark = pytest.mark.gpu
 
 def _sample_nodes(shape, tune, rng, count=24):
     nz, ny, nx = shape
-    by, zc = tune["block_y"], tune["z_chunk"]
+    bx, by, zc = tune["block_x"], tune["block_y"], tune["z_chunk"]
     zs = sorted({0, zc - 1, zc % nz, nz - 1, (2 * zc) % nz})
     ys = sorted({0, by - 1, by % ny, ny - 1, (ny // by // 2) * by % ny})
-    xs = sorted({0, nx - 1, nx // 2})
+    xs = sorted({0, bx - 1, bx % nx, nx - 1, nx // 2})
     nodes = [(z, y, x) for z in zs for y in ys for x in xs]
     pick = rng.choice(len(nodes), size=min(count, len(nodes)), replace=False)
     out = [nodes[i] for i in sorted(pick)]

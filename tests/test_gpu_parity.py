@@ -102,6 +102,10 @@ def test_config1_f32_shifted_1000_steps(coll, rho_ref):
     ((24, 24, 1), dict(threads=512, z_chunk=1)),
     ((7, 5, 3), dict(threads=256, block_y=2, z_chunk=2)),
     ((1024, 2, 4), None),
+    ((1100, 3, 2), None),
+    ((100, 9, 11), dict(threads=256, block_x=64, z_chunk=3)),
+    ((130, 7, 6), dict(threads=256, block_x=96, block_y=2, z_chunk=4)),
+    ((200, 5, 5), dict(threads=256, nodes_per_thread=2, block_x=70, z_chunk=2)),
 ])
 @pytest.mark.parametrize("coll", ["bgk", "mrt"])
 def test_ragged_shapes_f64(shape, tuning, coll):
@@ -113,14 +117,23 @@ def test_ragged_shapes_f64(shape, tuning, coll):
     assert float(np.abs(g["state"] - o["state"]).max()) < F64_TOL
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_launch_shape_does_not_change_results_bitwise(precision):
-    rho0 = gc.ligament(40, 36, 30, 8.0, 0.1, 1, noise=1e-4)
-    ref = None
-    for t in (None, dict(threads=256, z_chunk=3), dict(threads=512, block_y=1, z_chunk=30),
+_SHAPES_40 = (None, dict(threads=256, z_chunk=3), dict(threads=512, block_y=1, z_chunk=30),
               dict(threads=1024, xcd_remap=0, z_chunk=4), dict(threads=1024, block_y=5),
               dict(threads=256, nodes_per_thread=2, z_chunk=6),
-              dict(threads=512, nodes_per_thread=2, pop_pad=0)):
+              dict(threads=512, nodes_per_thread=2, pop_pad=0))
+# Tiles that split rows (block_x < nx, ragged last column of tiles) against
+# whole-row tiles.
+_SHAPES_150 = (None, dict(threads=256, block_x=64, z_chunk=5), dict(threads=512, block_x=150),
+               dict(threads=256, block_x=100, block_y=2, z_chunk=3),
+               dict(threads=512, nodes_per_thread=2, block_x=128, xcd_remap=0))
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("box,shapes", [((40, 36, 30), _SHAPES_40), ((150, 24, 10), _SHAPES_150)])
+def test_launch_shape_does_not_change_results_bitwise(precision, box, shapes):
+    rho0 = gc.ligament(*box, 8.0, 0.1, 1, noise=1e-4)
+    ref = None
+    for t in shapes:
         g = gc.run_gpu(rho0, 9, collision="mrt", precision=precision, tuning=t)
         if ref is None:
             ref = g["state"]
