@@ -50,6 +50,24 @@ def surface_tension(G):
     return table["%.4f" % G]["sigma_laplace"]["sigma"]
 
 
+def slab_density(nz, half_width, rho_v, rho_l, width=2.0):
+    """Planar liquid slab |z - nz/2| < half_width with tanh walls, [nz, 1, 1]
+    float64 (flat-interface runs, Sec. 3)."""
+    z = np.arange(nz, dtype=np.float64)
+    d = np.abs(z - nz / 2.0) - half_width
+    rho = 0.5 * (rho_l + rho_v) - 0.5 * (rho_l - rho_v) * np.tanh(2.0 * d / width)
+    return np.ascontiguousarray(rho.reshape(nz, 1, 1))
+
+
+def droplet_density(n, R, rho_v, rho_l, width=2.0):
+    """Static drop of radius R centred at (n/2, n/2, n/2) in a periodic n^3
+    box with a tanh wall (the Laplace test, Sec. 3), [n, n, n] float64."""
+    c = np.arange(n, dtype=np.float64) - n / 2.0
+    d = np.sqrt(c[:, None, None] ** 2 + c[None, :, None] ** 2 + c[None, None, :] ** 2)
+    return np.ascontiguousarray(0.5 * (rho_l + rho_v) - 0.5 * (rho_l - rho_v) *
+                                np.tanh(2.0 * (d - R) / width))
+
+
 def integer_mode(kR, R, nz):
     """Integer axial mode closest to kR in a periodic box of length nz."""
     m = max(1, int(round(kR * nz / (2.0 * math.pi * R))))
