@@ -9,6 +9,9 @@ Break-up criterion (the paper does not state one): the first sampled step at
 which some z-slice holds no node denser than the mid density
 (rho_l + rho_v) / 2, i.e. the liquid column is cut.  Sampling every `every`
 steps bounds the resolution of T_break to every / t_cap.
+
+`Recorder` samples the observables of Sec. 4 along the run (perturbation
+growth, silhouettes, minimum radius, velocity magnitude maps).
 """
 import numpy as np
 import torch
@@ -35,46 +38,137 @@ def neck_cut(sim, rho_mid):
     return bool((slice_max <= rho_mid).any())
 
 
-def break_time(R0, operator, eps=0.1, every=25, max_tcap=12.0, precision="f32", progress=False):
-    """(T_break / t_cap, steps, info) for the paper's run at radius R0."""
+class Recorder:
+    """Observables of Sec. 4 sampled along a run (every `every` steps):
+
+    * r(z, t), the equivalent radius of each slice (interface diagnostics);
+      from it the minimum radius h_min(t) / R0 (Fig. 5) and the perturbation
+      at the neck z = L/4 and at the crest z = 0, each normalised by its
+      initial value (Fig. 4a: our cos profile puts the neck at L/4 where the
+      paper's sin profile has it at 3 L/8);
+    * silhouettes r(z) at the requested t* = t / t_cap (Fig. 4b: 7, 8, 9);
+    * v* = |u^b| / (R0 / t_cap) on the plane through the axis (y = ny/2) at
+      the requested t* (Fig. 6), float32 [nz, nx].
+    """
+
+    def __init__(self, info, silhouette_tstar=(7.0, 8.0, 9.0), velocity_tstar=(7.0, 8.0, 9.0)):
+        self.info = info
+        self.t, self.r = [], []
+        self.sil_t = sorted(silhouette_tstar)
+        self.vel_t = sorted(velocity_tstar)
+        self.silhouettes, self.velocity = {}, {}
+
+    def sample(self, sim, steps, last=False):
+        info = self.info
+        tstar = steps / info["t_cap"]
+        d = sim.diagnostics(info["rho_v"], info["rho_l"])
+        self.t.append(steps)
+        self.r.append(np.asarray(d["r_of_z"], dtype=np.float64))
+        for ts in self.sil_t:
+            if ts not in self.silhouettes and tstar >= ts:
+                self.silhouettes[ts] = (steps, self.r[-1].copy())
+        for ts in self.vel_t:
+            if ts not in self.velocity and (tstar >= ts or last):
+                _, u, _ = sim.moments(want_u=True, want_p=False)
+                mid = info["ny"] // 2
+                vmag = torch.sqrt((u[:, :, mid, :] ** 2).sum(0))
+                v = (vmag / (info["R0"] / info["t_cap"])).float().cpu().numpy()
+                self.velocity[ts] = (steps, v)
+                break
+
+    def result(self):
+        info = self.info
+        r = np.stack(self.r)
+        t = np.asarray(self.t, dtype=np.float64)
+        nz = r.shape[1]
+        rbar = r[0].mean()
+        neck, crest = nz // 4, 0
+        return {
+            "t_star": t / info["t_cap"],
+            "h_min_over_R0": r.min(axis=1) / info["R0"],
+            "neck_perturbation": (rbar - r[:, neck]) / (rbar - r[0, neck]),
+            "crest_perturbation": (r[:, crest] - rbar) / (r[0, crest] - rbar),
+            "r_of_z": r,
+            "silhouettes": {k: v for k, v in self.silhouettes.items()},
+            "velocity": {k: v for k, v in self.velocity.items()},
+        }
+
+
+def break_time(R0, operator, eps=0.1, every=25, max_tcap=16.0, precision="f32", progress=False,
+               record=None):
+    """(T_break / t_cap, steps, info) for the paper's run at radius R0.
+    With record = a Recorder (or True for the default one), info["record"]
+    holds the observables it sampled."""
     rho0, info = lbm_inputs.paper_ligament(R0, operator, eps)
     sim = lbsc.Simulation(rho0, params_for(info, operator, precision))
+    rec = Recorder(info) if record is True else record
     rho_mid = 0.5 * (info["rho_l"] + info["rho_v"])
     max_steps = int(max_tcap * info["t_cap"])
     steps = 0
     broke = False
+    if rec is not None:
+        rec.sample(sim, 0)
     while steps < max_steps:
         sim.step(every)
         steps += every
-        if neck_cut(sim, rho_mid):
+        cut = neck_cut(sim, rho_mid)
+        if rec is not None:
+            rec.sample(sim, steps, last=cut)
+        if cut:
             broke = True
             break
         if progress and steps % 2000 == 0:
-            print("  R0=%d %s: %d steps (%.2f t_cap)" % (R0, operator, steps,
-                                                       steps / info["t_cap"]), flush=True)
+            print("  R0=%d %s eps=%.4f: %d steps (%.2f t_cap)" % (R0, operator, eps, steps,
+                                                                 steps / info["t_cap"]),
+                  flush=True)
     torch.cuda.synchronize()
     sim.close()
     info = dict(info, steps=steps, broke=broke, every=every)
+    if rec is not None:
+        info["record"] = rec.result()
     return (steps / info["t_cap"] if broke else float("nan")), steps, info
+
+
+def save_record(path, info):
+    """Writes the observables of one run to an .npz file."""
+    r = info["record"]
+    arrays = {k: r[k] for k in ("t_star", "h_min_over_R0", "neck_perturbation",
+                                "crest_perturbation")}
+    arrays["r_of_z"] = r["r_of_z"].astype(np.float32)
+    for ts, (st, prof) in r["silhouettes"].items():
+        arrays["silhouette_t%g" % ts] = prof
+    for ts, (st, v) in r["velocity"].items():
+        arrays["vstar_t%g_step%d" % (ts, st)] = v
+    np.savez_compressed(path, **arrays)
 
 
 def main():
     import argparse
     import json
+    import os
     ap = argparse.ArgumentParser()
     ap.add_argument("--radii", default="14,28,42,56")
     ap.add_argument("--operators", default="mrt,srt")
-    ap.add_argument("--eps", type=float, default=0.1)
+    ap.add_argument("--eps", default="0.1", help="comma-separated delta / R0 values")
     ap.add_argument("--every", type=int, default=25)
+    ap.add_argument("--record", default=None,
+                    help="folder for per-run .npz files of the observables (Figs. 4-6)")
     args = ap.parse_args()
     out = []
     for op in args.operators.split(","):
         for R0 in (int(r) for r in args.radii.split(",")):
-            t, steps, info = break_time(R0, op, args.eps, args.every, progress=True)
-            rec = {"operator": op, "R0": R0, "eps": args.eps, "T_break_over_tcap": t,
-                   "steps": steps, "box": [info["nx"], info["ny"], info["nz"]]}
-            print(json.dumps(rec), flush=True)
-            out.append(rec)
+            for eps in (float(e) for e in args.eps.split(",")):
+                t, steps, info = break_time(R0, op, eps, args.every, progress=True,
+                                            record=bool(args.record))
+                rec = {"operator": op, "R0": R0, "eps": eps, "T_break_over_tcap": t,
+                       "steps": steps, "box": [info["nx"], info["ny"], info["nz"]]}
+                if args.record:
+                    os.makedirs(args.record, exist_ok=True)
+                    path = os.path.join(args.record, "breakup_%s_R%d_eps%.4f.npz" % (op, R0, eps))
+                    save_record(path, info)
+                    rec["record"] = path
+                print(json.dumps(rec), flush=True)
+                out.append(rec)
     return out
 
 

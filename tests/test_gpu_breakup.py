@@ -10,6 +10,8 @@ criterion, sampling every 25 steps); the differences shrink with R0 (below
 """
 import pytest
 
+import lbm_inputs
+
 pytestmark = pytest.mark.gpu
 
 # Fig. 2b of the paper: T_break / t_cap
@@ -31,3 +33,51 @@ def test_breakup_times_match_fig2b():
         assert got[(op, 28)] > got[(op, 14)]
     for R0 in (14, 28):
         assert got[("srt", R0)] > got[("mrt", R0)]
+
+
+def test_observables_of_the_run():
+    """Recorder output on the R0 = 14 runs (Sec. 4): the neck perturbation of
+    both operators follows the same early curve (Fig. 4a), the minimum radius
+    falls to the break-up, silhouettes and v* maps come at the requested
+    times."""
+    import numpy as np
+    from paper_1905_09554_amd import breakup
+    recs = {}
+    for op in ("mrt", "srt"):
+        rho0, info = lbm_inputs.paper_ligament(14, op, 0.1)
+        rec = breakup.Recorder(info, silhouette_tstar=(2.0, 4.0), velocity_tstar=(4.0, 5.0))
+        t, steps, info = breakup.break_time(14, op, record=rec)
+        r = info["record"]
+        recs[op] = r
+        assert set(r["silhouettes"]) == {2.0, 4.0}
+        assert set(r["velocity"]) == {4.0, 5.0}
+        for st, v in r["velocity"].values():
+            assert v.shape == (info["nz"], info["nx"]) and np.isfinite(v).all()
+        h = r["h_min_over_R0"]
+        assert h[0] > 0.85 and h[-1] < 0.3
+        assert r["neck_perturbation"][0] == 1.0
+        print("%s: T %.3f, neck perturbation at t*=2,4: %.3f %.3f" % (
+            op, t, np.interp(2, r["t_star"], r["neck_perturbation"]),
+            np.interp(4, r["t_star"], r["neck_perturbation"])), flush=True)
+    for ts in (1.0, 2.0, 3.0, 4.0):
+        a = np.interp(ts, recs["mrt"]["t_star"], recs["mrt"]["neck_perturbation"])
+        b = np.interp(ts, recs["srt"]["t_star"], recs["srt"]["neck_perturbation"])
+        assert a > 1.0 and b > 1.0 and abs(a / b - 1) < 0.1, (ts, a, b)
+
+
+def test_perturbation_sweep_against_linear_theory():
+    """Fig. 3 in miniature (R0 = 28, MRT): halving the initial perturbation
+    delays the break-up by ln(2) / omega, omega t_cap = 0.28 in the paper's
+    linear-stability curve.  The pseudo-potential ligament grows a little
+    faster than sharp-interface theory at this radius (the dispersion sweep
+    gives 1.05-1.17 times the theory near R = 24-30), so the delay may fall up
+    to 25 % short of the prediction (measured: 17 % short)."""
+    import math
+    from paper_1905_09554_amd import breakup
+    t10, _, _ = breakup.break_time(28, "mrt", eps=0.1)
+    t05, _, _ = breakup.break_time(28, "mrt", eps=0.05)
+    delay = t05 - t10
+    lsa = math.log(2.0) / 0.28
+    print("R0=28 MRT: T(0.1) %.3f, T(0.05) %.3f, delay %.3f (linear theory %.3f)"
+          % (t10, t05, delay, lsa), flush=True)
+    assert 0.75 * lsa < delay < 1.1 * lsa
