@@ -101,7 +101,7 @@ def break_time(R0, operator, eps=0.1, every=25, max_tcap=16.0, precision="f32", 
     holds the observables it sampled."""
     rho0, info = lbm_inputs.paper_ligament(R0, operator, eps)
     sim = lbsc.Simulation(rho0, params_for(info, operator, precision))
-    rec = Recorder(info) if record is True else record
+    rec = Recorder(info) if record is True else (record or None)
     rho_mid = 0.5 * (info["rho_l"] + info["rho_v"])
     max_steps = int(max_tcap * info["t_cap"])
     steps = 0

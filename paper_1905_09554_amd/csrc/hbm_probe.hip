@@ -1,6 +1,6 @@
 // HBM bandwidth calibration: what plain streaming kernels reach on this GPU.
 // It is the denominator next to the 8 TB/s datasheet peak when the step's
-// achieved bandwidth is judged.  Prints one line per kernel and launch shape.
+// achieved bandwidth is compared.  Prints one line per kernel and launch shape.
 //
 //   paper_1905_09554_amd/hbm_probe
 //

@@ -1,0 +1,114 @@
+"""Host-side logic of the drivers, without a GPU: fits, closed forms, launch
+shape candidates, observable bookkeeping and input builders."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs
+
+
+def test_tau_for_ohnesorge_inverts_eq_oh_tcap():
+    from paper_1905_09554_amd import calibration
+    for rl, sigma, R0, oh in ((2.1086, 0.0495, 14, 0.1), (2.1775, 0.08991, 98, 0.1),
+                              (1.9, 0.035, 30, 0.25)):
+        tau = calibration.tau_for_ohnesorge(oh, rl, sigma, R0)
+        nu = (tau - 0.5) / 3.0
+        assert abs(rl * nu / math.sqrt(rl * sigma * R0) - oh) < 1e-14
+    # Table 2 (MRT, sigma independent of tau): tau of the R0 = 14 column.
+    t = lbm_inputs.PAPER_TABLE["mrt"]
+    tau = calibration.tau_for_ohnesorge(0.1, t["rho_l"][0], t["sigma"][0], 14)
+    assert abs(tau / t["tau"][0] - 1) < 0.005
+
+
+def test_autotune_candidates_are_valid_shapes():
+    from paper_1905_09554_amd import autotune
+    for nx, prec in ((256, "f32"), (256, "f64"), (32, "f64"), (600, "f32")):
+        cands = autotune.candidates(nx, prec)
+        assert cands
+        for c in cands:
+            cap = c["threads"] * c["nodes_per_thread"]
+            assert c["block_x"] <= min(nx, cap)
+            if c["block_x"] < nx:
+                assert c["block_x"] % 64 == 0 and 2 * c["block_x"] <= cap
+            if prec == "f64":
+                assert c["threads"] <= 512 and c["nodes_per_thread"] == 1
+
+
+def test_growth_fit_recovers_an_exponential():
+    from paper_1905_09554_amd import dispersion
+    t = np.arange(0, 5000, 50.0)
+    a = 0.3 * np.exp(4e-4 * t)
+    assert abs(dispersion.fit_growth(t, a, R=30, t_start=1000) - 4e-4) < 1e-12
+    # the window stops at a <= 0.15 R: too few samples left -> None
+    assert dispersion.fit_growth(t, a, R=30, t_start=4900) is None
+
+
+def test_mode_amplitude_of_a_cosine():
+    from paper_1905_09554_amd import dispersion
+    nz = 96
+    z = np.arange(nz)
+    r = 20.0 + 0.7 * np.cos(2 * math.pi * z / nz) + 0.3 * np.cos(4 * math.pi * z / nz)
+    assert abs(dispersion.mode_amplitude(r) - 0.7) < 1e-12
+
+
+class _FakeSim:
+    """Stands in for lbsc.Simulation: a radius profile that narrows at the
+    neck z = nz/4 and a uniform velocity field."""
+
+    def __init__(self, info):
+        self.info = info
+        self.k = 0
+
+    def diagnostics(self, rho_v, rho_l):
+        nz = self.info["nz"]
+        z = np.arange(nz)
+        amp = 1.0 + 0.1 * self.k
+        r = self.info["R0"] * (1.0 + 0.1 * amp * np.cos(4 * math.pi * z / nz))
+        return {"r_of_z": r}
+
+    def moments(self, want_u=True, want_p=False):
+        i = self.info
+        u = torch.zeros((3, i["nz"], i["ny"], i["nx"]), dtype=torch.float64)
+        u[2] = 0.01
+        return None, u, None
+
+
+def test_recorder_bookkeeping():
+    from paper_1905_09554_amd import breakup
+    info = {"nx": 8, "ny": 8, "nz": 64, "R0": 14, "t_cap": 100.0, "rho_v": 0.08, "rho_l": 2.1}
+    rec = breakup.Recorder(info, silhouette_tstar=(1.0, 2.0), velocity_tstar=(1.5,))
+    sim = _FakeSim(info)
+    for k in range(0, 26):
+        sim.k = k
+        rec.sample(sim, 10 * k, last=(k == 25))
+    r = rec.result()
+    assert r["t_star"][0] == 0.0 and abs(r["t_star"][-1] - 2.5) < 1e-12
+    # perturbation amplitude 1 + 0.1 k, normalised by its initial value
+    assert np.allclose(r["neck_perturbation"], 1.0 + 0.1 * np.arange(26))
+    assert np.allclose(r["crest_perturbation"], 1.0 + 0.1 * np.arange(26))
+    assert sorted(r["silhouettes"]) == [1.0, 2.0]
+    assert r["silhouettes"][1.0][0] == 100 and r["silhouettes"][2.0][0] == 200
+    st, v = r["velocity"][1.5]
+    assert st == 150 and v.shape == (64, 8)
+    assert np.allclose(v, 0.01 / (14 / 100.0))
+    assert abs(r["h_min_over_R0"][0] - 0.9) < 1e-12
+
+
+def test_droplet_and_slab_inputs():
+    d = lbm_inputs.droplet_density(24, 6.0, 0.1, 2.0)
+    assert d.shape == (24, 24, 24)
+    assert d[12, 12, 12] > 1.99 and d[0, 0, 0] < 0.11
+    assert np.allclose(d, d.transpose(1, 0, 2)) and np.allclose(d, d.transpose(2, 1, 0))
+    s = lbm_inputs.slab_density(32, 8, 0.1, 2.0)
+    assert s.shape == (32, 1, 1) and s[16, 0, 0] > 1.99 and s[0, 0, 0] < 0.11
+
+
+@pytest.mark.parametrize("R0,op", [(14, "mrt"), (28, "srt")])
+def test_paper_ligament_geometry(R0, op):
+    rho, info = lbm_inputs.paper_ligament(R0, op)
+    assert rho.shape == (256 * R0 // 14, 96 * R0 // 14, 96 * R0 // 14)
+    assert info["nz"] == 256 * R0 // 14
+    # k R0 of two wavelengths in L_x is the fastest mode, 4 pi 14 / 256
+    assert abs(4 * math.pi * R0 / info["nz"] - 0.687) < 0.001
