@@ -43,15 +43,29 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def launch_shape_entry(workload, precision):
+    """The autotuner's launch shape for a single-box workload (None: the
+    library default)."""
+    import lbm_inputs
+    from paper_1905_09554_amd import lbsc, tuning
+    w = lbm_inputs.WORKLOADS[workload]
+    prm = lbsc.make_params(w["nx"], w["ny"], w["nz"], collision=w["collision"],
+                           precision=precision)
+    return tuning.lookup(prm)
+
+
 def measured_traffic(workload, precision):
     """HBM bytes per step-kernel launch from the committed rocprofv3 counter
-    runs, or None when absent or taken on different kernel sources."""
+    runs, or None when absent or taken on different kernel sources or with a
+    different launch shape."""
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (workload, precision))
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
     if rec.get("source_hash") != kernel_source_hash():
+        return None
+    if rec.get("launch_shape", "missing") != launch_shape_entry(workload, precision):
         return None
     return rec.get("bytes_per_launch")
 

@@ -10,7 +10,8 @@ Both counters are in KiB per dispatch.  Each is scaled by what it reads for
 the driver's plain copy of a known size (1 GiB read, 1 GiB written), and the
 per-launch bytes of the step kernel are written to
 profiles/traffic_<workload>_<precision>.json together with a hash of the
-kernel sources (the benchmark ignores the file once the sources change).
+kernel sources and the autotuner's launch shape for the box (the benchmark
+ignores the file once either changes).
 """
 import argparse
 import csv
@@ -56,7 +57,7 @@ def main():
 
     import sys
     sys.path.insert(0, ROOT)
-    from bench import kernel_source_hash
+    from bench import kernel_source_hash, launch_shape_entry
 
     f_step, f_copy, nf = _per_kernel(_rows(args.fetch, "FETCH_SIZE"))
     w_step, w_copy, nw = _per_kernel(_rows(args.write, "WRITE_SIZE"))
@@ -69,6 +70,7 @@ def main():
     rec = {
         "workload": args.workload, "precision": args.precision, "nodes": args.nodes,
         "source_hash": kernel_source_hash(),
+        "launch_shape": launch_shape_entry(args.workload, args.precision),
         "fetch_kib_raw": f_step, "write_kib_raw": w_step, "dispatches": [nf, nw],
         "copy_fetch_kib": f_copy, "copy_write_kib": w_copy,
         "fetch_scale": f_scale, "write_scale": w_scale,
