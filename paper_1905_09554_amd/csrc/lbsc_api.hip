@@ -148,21 +148,25 @@ int check_batch(int32_t n, const lbsc_params* p, std::string* msg) {
 // Tile of the fused step: bx columns by by rows, at most cap = npt * threads
 // nodes.  Each plane of the z-march also reloads the tile's halo ring, one
 // node per thread; a ring larger than the work-group costs a second round of
-// dependent loads.  Default bx: whole rows when the group holds two or more
-// of them and their two halo rows fit one round (2 nx <= threads); else the
-// widest multiple of 64 columns whose ring, 2 (bx + 2) + 2 by, fits one
-// round with by = cap / bx >= 2 rows.  Four psi planes of (by + 2)(bx + 2)
-// values must fit the 160 KB of LDS of a CU.
-int default_block_x(int nx, long long cap, int threads) {
-  if (2LL * nx <= cap && 2LL * nx <= threads) return nx;
-  for (long long bx = std::min<long long>(nx, cap / 2) / 64 * 64; bx >= 64; bx -= 64)
-    if (2 * (bx + 2) + 2 * (cap / bx) <= threads) return (int)bx;
+// dependent loads.  Default bx: whole rows when the group holds at least
+// min_rows of them and their two halo rows fit one round (2 nx <= threads);
+// else the widest multiple of 64 columns whose ring, 2 (bx + 2) + 2 by, fits
+// one round with by = cap / bx >= min_rows; else the same with two rows.
+// float64 tiles want four rows (measured: 64 x 4 beats whole rows two deep
+// at 256 threads), float32 two.  Four psi planes of (by + 2)(bx + 2) values
+// must fit the 160 KB of LDS of a CU.
+int default_block_x(int nx, long long cap, int threads, int min_rows) {
+  for (int rows = min_rows; rows >= 2; rows /= 2) {
+    if ((long long)rows * nx <= cap && 2LL * nx <= threads) return nx;
+    for (long long bx = std::min<long long>(nx, cap / rows) / 64 * 64; bx >= 64; bx -= 64)
+      if (2 * (bx + 2) + 2 * (cap / bx) <= threads) return (int)bx;
+  }
   return std::min<int>(nx, 64);
 }
 
 void tile_shape(int nx, int ny, long long cap, int threads, int block_x, int block_y, size_t elem,
                 int* bx_out, int* by_out) {
-  int bx = block_x > 0 ? block_x : default_block_x(nx, cap, threads);
+  int bx = block_x > 0 ? block_x : default_block_x(nx, cap, threads, elem == 8 ? 4 : 2);
   if (bx > nx) bx = nx;
   if (bx > cap) bx = (int)cap;
   const int rows = (int)std::max(1LL, cap / bx);
@@ -202,29 +206,53 @@ lbsc::StepArgs make_args(const lbsc_params& p, const lbsc_tuning& t, long long p
 
 long long pad_of(const lbsc_tuning& t) { return t.pop_pad >= 0 ? t.pop_pad : kDefaultPad; }
 
+// xy tiles times planes over all members: the number of work-groups with
+// one-plane chunks.
+long long tile_columns(const lbsc_params* p, int32_t n, int threads) {
+  long long columns = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    int bx = 1, by = 1;
+    tile_shape(p[i].nx, p[i].ny, threads, threads, 0, 0, elem_size(p[i]), &bx, &by);
+    columns += (long long)((p[i].nx + bx - 1) / bx) * ((p[i].ny + by - 1) / by) * p[i].nz;
+  }
+  return columns;
+}
+
 lbsc_tuning default_tuning(const lbsc_params* p, int32_t n) {
   lbsc_tuning t;
-  // Two or more work-groups per CU overlap one group's loads with another's
-  // collision; float64 needs twice the registers, so smaller groups.
-  t.threads = p[0].precision == LBSC_F64 ? 256 : 512;
   t.block_x = 0;
   t.block_y = 0;
   t.xcd_remap = 1;
   t.pop_pad = -1;
   t.nodes_per_thread = 1;
   t.persistent = 0;
-  // About two work-groups per CU (512 in all): long z-marches keep the two
-  // extra halo planes of each chunk a small fraction on large boxes, short
-  // ones give small boxes enough groups.
-  long long columns = 0;  // xy tiles times planes, over all members
-  for (int32_t i = 0; i < n; ++i) {
-    int bx = 1, by = 1;
-    tile_shape(p[i].nx, p[i].ny, t.threads, t.threads, 0, 0, elem_size(p[i]), &bx, &by);
-    columns += (long long)((p[i].nx + bx - 1) / bx) * ((p[i].ny + by - 1) / by) * p[i].nz;
+  // float64 (about 200 VGPRs, 2 waves per SIMD): 256-thread groups, two per
+  // CU, so one group's loads overlap the other's collision.  float32 (about
+  // 110 VGPRs): 512-thread groups, two per CU; boxes with rows of at most 256
+  // nodes and enough tiles run 1024-thread groups of whole rows four or more
+  // deep instead, one per CU (measured: 32.0 against 29.3 GLUPS on
+  // 256 x 256 x 1024, 29.9 against 27.9 on 128 x 128 x 512, 27.5 against
+  // 26.1 on the 64-ligament batch): the deeper tile's smaller halo ring
+  // outweighs the lost overlap.
+  int nx = 1;
+  for (int32_t i = 0; i < n; ++i) nx = std::max(nx, p[i].nx);
+  if (p[0].precision == LBSC_F64) {
+    t.threads = 256;
+  } else {
+    t.threads = 512;
+    if (4 * nx <= 1024 && tile_columns(p, n, 1024) >= 256LL * 16) t.threads = 1024;
   }
-  long long zc = (columns + 511) / 512;
+  // Chunk length.  A single box on 1024-thread groups: one wave of 256 groups,
+  // one per CU (no tail), up to 256 planes.  Otherwise about 512 groups of 1
+  // to 64 planes: long marches keep the two extra halo planes of each chunk a
+  // small fraction on large boxes, short ones give small boxes enough groups.
+  const long long columns = tile_columns(p, n, t.threads);
+  const bool one_wave = t.threads == 1024 && n == 1;
+  const long long groups = one_wave ? 256 : 512;
+  const long long zmax = one_wave ? 256 : 64;
+  long long zc = (columns + groups - 1) / groups;
   if (zc < 1) zc = 1;
-  if (zc > 64) zc = 64;
+  if (zc > zmax) zc = zmax;
   t.z_chunk = (int)zc;
   return t;
 }
