@@ -33,9 +33,42 @@ def params_for(info, operator, precision="f32"):
 
 def neck_cut(sim, rho_mid):
     """True if some z-slice has no node above rho_mid."""
+    return bool((slice_max(sim) <= rho_mid).any())
+
+
+def slice_max(sim):
+    """Densest node of every z-slice, float64 numpy [nz]."""
     rho, _, _ = sim.moments(want_u=False, want_p=False)
-    slice_max = rho.amax(dim=(1, 2))
-    return bool((slice_max <= rho_mid).any())
+    return rho.amax(dim=(1, 2)).cpu().numpy()
+
+
+def drops(smax, rho_mid, r_of_z=None):
+    """Liquid bodies along the periodic axis: maximal runs of slices whose
+    densest node exceeds rho_mid.  Returns a list of (first slice, length,
+    volume) with volume = sum of pi r(z)^2 over the run when r(z) is given."""
+    wet = np.asarray(smax) > rho_mid
+    nz = len(wet)
+    if wet.all():
+        return [(0, nz, float(np.pi * np.sum(np.asarray(r_of_z) ** 2)) if r_of_z is not None
+                 else None)]
+    if not wet.any():
+        return []
+    start = int(np.argmin(wet))  # a dry slice: runs never wrap across it
+    out = []
+    z = 0
+    while z < nz:
+        k = (start + z) % nz
+        if wet[k]:
+            n = 0
+            while z + n < nz and wet[(start + z + n) % nz]:
+                n += 1
+            idx = [(k + i) % nz for i in range(n)]
+            vol = float(np.pi * np.sum(np.asarray(r_of_z)[idx] ** 2)) if r_of_z is not None else None
+            out.append((k, n, vol))
+            z += n
+        else:
+            z += 1
+    return out
 
 
 class Recorder:
@@ -95,10 +128,14 @@ class Recorder:
 
 
 def break_time(R0, operator, eps=0.1, every=25, max_tcap=16.0, precision="f32", progress=False,
-               record=None):
+               record=None, after_tcap=0.0):
     """(T_break / t_cap, steps, info) for the paper's run at radius R0.
     With record = a Recorder (or True for the default one), info["record"]
-    holds the observables it sampled."""
+    holds the observables it sampled.  With after_tcap > 0 the run goes on
+    for that many capillary times after the break-up and info["drops"] holds
+    the liquid bodies along the axis at every sample (see `satellites`); a
+    state that turns non-finite ends the continuation and is reported as
+    info["diverged_after_tcap"]."""
     rho0, info = lbm_inputs.paper_ligament(R0, operator, eps)
     sim = lbsc.Simulation(rho0, params_for(info, operator, precision))
     rec = Recorder(info) if record is True else (record or None)
@@ -121,12 +158,60 @@ def break_time(R0, operator, eps=0.1, every=25, max_tcap=16.0, precision="f32", 
             print("  R0=%d %s eps=%.4f: %d steps (%.2f t_cap)" % (R0, operator, eps, steps,
                                                                  steps / info["t_cap"]),
                   flush=True)
+    history = []
+    diverged = None
+    if broke and after_tcap > 0:
+        end = steps + int(after_tcap * info["t_cap"])
+        t = steps
+        while t < end:
+            sim.step(every)
+            t += every
+            try:
+                d = sim.diagnostics(info["rho_v"], info["rho_l"])
+            except lbsc.LbscError as e:
+                if e.code != lbsc.LBSC_ENONFINITE:
+                    raise
+                diverged = t  # the state holds NaN or Inf: stop here
+                break
+            history.append((t, drops(slice_max(sim), rho_mid, d["r_of_z"])))
     torch.cuda.synchronize()
     sim.close()
     info = dict(info, steps=steps, broke=broke, every=every)
+    if diverged is not None:
+        info["diverged_after_tcap"] = (diverged - steps) / info["t_cap"]
     if rec is not None:
         info["record"] = rec.result()
+    if history:
+        info["drops"] = history
+        info["satellites"] = satellites(history, info)
     return (steps / info["t_cap"] if broke else float("nan")), steps, info
+
+
+def satellites(history, info, frac=0.25):
+    """Satellite droplets after the break-up: bodies whose volume is below
+    `frac` of the largest body's.  Returns the largest number of them seen
+    at one time, the number left at the end, and the longest unbroken
+    stretch (in capillary times) during which at least one was present (the
+    paper calls satellites stable when they live at least one capillary
+    time)."""
+    counts = []
+    for t, bodies in history:
+        vols = [b[2] for b in bodies]
+        big = max(vols) if vols else 0.0
+        counts.append((t, sum(1 for v in vols if v < frac * big)))
+    if not counts:
+        return {"max": 0, "final": 0, "life_tcap": 0.0, "bodies_final": 0}
+    longest, start = 0.0, None
+    for t, c in counts:
+        if c > 0 and start is None:
+            start = t
+        if c == 0 and start is not None:
+            longest = max(longest, t - start)
+            start = None
+    if start is not None:
+        longest = max(longest, counts[-1][0] - start)
+    return {"max": max(c for _, c in counts), "final": counts[-1][1],
+            "life_tcap": longest / info["t_cap"], "bodies_final": len(history[-1][1])}
 
 
 def save_record(path, info):
@@ -153,15 +238,23 @@ def main():
     ap.add_argument("--every", type=int, default=25)
     ap.add_argument("--record", default=None,
                     help="folder for per-run .npz files of the observables (Figs. 4-6)")
+    ap.add_argument("--after", type=float, default=0.0,
+                    help="capillary times to keep running after the break-up (satellites)")
     args = ap.parse_args()
     out = []
     for op in args.operators.split(","):
         for R0 in (int(r) for r in args.radii.split(",")):
             for eps in (float(e) for e in args.eps.split(",")):
                 t, steps, info = break_time(R0, op, eps, args.every, progress=True,
-                                            record=bool(args.record))
+                                            record=bool(args.record), after_tcap=args.after)
                 rec = {"operator": op, "R0": R0, "eps": eps, "T_break_over_tcap": t,
                        "steps": steps, "box": [info["nx"], info["ny"], info["nz"]]}
+                if "diverged_after_tcap" in info:
+                    rec["diverged_after_tcap"] = info["diverged_after_tcap"]
+                if "satellites" in info:
+                    rec["satellites"] = info["satellites"]
+                    rec["bodies_after"] = [[round(b[2], 1) for b in bodies]
+                                           for _, bodies in info["drops"][::10]]
                 if args.record:
                     os.makedirs(args.record, exist_ok=True)
                     path = os.path.join(args.record, "breakup_%s_R%d_eps%.4f.npz" % (op, R0, eps))

@@ -112,3 +112,27 @@ def test_paper_ligament_geometry(R0, op):
     assert info["nz"] == 256 * R0 // 14
     # k R0 of two wavelengths in L_x is the fastest mode, 4 pi 14 / 256
     assert abs(4 * math.pi * R0 / info["nz"] - 0.687) < 0.001
+
+
+def test_drop_segmentation_and_satellites():
+    from paper_1905_09554_amd import breakup
+    r = np.full(20, 2.0)
+    r[6:8] = 1.0
+    smax = np.where(np.isin(np.arange(20), [4, 5, 9, 10, 14]), 0.05, 2.0)
+    bodies = breakup.drops(smax, 1.0, r)
+    # runs: 15..3 (wraps), 6..8, 11..13
+    assert [(b[0], b[1]) for b in bodies] == [(6, 3), (11, 3), (15, 9)]
+    assert abs(bodies[0][2] - math.pi * (1 + 1 + 4)) < 1e-12
+    info = {"t_cap": 100.0}
+    big = (0, 9, 100.0)
+    sat = (0, 2, 5.0)
+    # satellites from the sample at t = 50 to the first sample without them
+    # (150): 1.0 t_cap; again from 200 to the end of the run (300): 1.0
+    history = [(0, [big, big]), (50, [big, sat, big]), (100, [big, sat, big, sat]),
+               (150, [big, big]), (200, [big, sat, big]), (300, [big, sat, big])]
+    s = breakup.satellites(history, info)
+    assert s["max"] == 2 and s["final"] == 1 and abs(s["life_tcap"] - 1.0) < 1e-12
+    assert s["bodies_final"] == 3
+    # a satellite that outlives the run is counted up to the last sample
+    s = breakup.satellites([(0, [big]), (100, [big, sat]), (400, [big, sat])], info)
+    assert abs(s["life_tcap"] - 3.0) < 1e-12
