@@ -240,14 +240,17 @@ def main():
                     help="folder for per-run .npz files of the observables (Figs. 4-6)")
     ap.add_argument("--after", type=float, default=0.0,
                     help="capillary times to keep running after the break-up (satellites)")
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     args = ap.parse_args()
     out = []
     for op in args.operators.split(","):
         for R0 in (int(r) for r in args.radii.split(",")):
             for eps in (float(e) for e in args.eps.split(",")):
-                t, steps, info = break_time(R0, op, eps, args.every, progress=True,
-                                            record=bool(args.record), after_tcap=args.after)
-                rec = {"operator": op, "R0": R0, "eps": eps, "T_break_over_tcap": t,
+                t, steps, info = break_time(R0, op, eps, args.every, precision=args.precision,
+                                            progress=True, record=bool(args.record),
+                                            after_tcap=args.after)
+                rec = {"operator": op, "R0": R0, "eps": eps, "precision": args.precision,
+                       "T_break_over_tcap": t,
                        "steps": steps, "box": [info["nx"], info["ny"], info["nz"]]}
                 if "diverged_after_tcap" in info:
                     rec["diverged_after_tcap"] = info["diverged_after_tcap"]
