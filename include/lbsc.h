@@ -231,6 +231,15 @@ int lbsc_rmin_gradient(lbsc_ctx* c, double rho_v, double rho_l, double* rhobar_d
 int lbsc_adjoint_backward(lbsc_ctx* c, const double* rhobar_dev, double* rho0bar_dev,
                           double* dL_dG, double* dL_dtau);
 
+/* Gradients of the last lbsc_adjoint_backward with respect to the MRT bulk
+ * and ghost relaxation rates s_bulk and s_ghost of lbsc_params (the rates of
+ * the d'Humieres rows other than the shear rows, Sec. 2 MRT paragraph; both
+ * 0 for BGK).  dL/dtau covers the shear rates 1/tau only: a caller that ties
+ * s_bulk to 1/tau, as the paper's rate set does, adds
+ * dL/ds_bulk * (-1/tau^2) itself.  Host outputs, either may be NULL.
+ * LBSC_ESTATE before the first backward pass. */
+int lbsc_adjoint_rate_gradients(const lbsc_ctx* c, double* dL_ds_bulk, double* dL_ds_ghost);
+
 /* Overrides the launch shape of the fused step (see lbsc_tuning). */
 int lbsc_set_tuning(lbsc_ctx* c, const lbsc_tuning* t);
 int lbsc_get_tuning(const lbsc_ctx* c, lbsc_tuning* t);

@@ -3,7 +3,8 @@
 Test infrastructure only.  The loss is the minimum ligament radius after a
 number of steps (Sec. 4, Fig. 5: the smallest radial coordinate of the
 interface, here r(z) = sqrt(A(z)/pi) as in ``diagnostics``).  torch autograd
-through the whole oracle run gives dL/drho0, dL/dG and dL/dtau; segments are
+through the whole oracle run gives dL/drho0, dL/dG and dL/dtau, and for MRT
+dL/ds_bulk and dL/ds_ghost (the bulk and ghost relaxation rates); segments are
 wrapped in ``torch.utils.checkpoint`` so memory stays bounded, which does not
 change the arithmetic.
 
@@ -47,3 +48,14 @@ def rmin_gradients(rho0, G, tau, steps, rho_v, rho_l, **kw):
     loss = rmin_after(rho0, Gt, taut, steps, rho_v, rho_l, **kw)
     loss.backward()
     return float(loss.detach()), rho0.grad.detach(), float(Gt.grad), float(taut.grad)
+
+
+def rmin_rate_gradients(rho0, G, tau, steps, rho_v, rho_l, s_bulk, s_ghost, segment=25):
+    """(r_min, dL/ds_bulk, dL/ds_ghost) of the MRT run by autograd."""
+    sb = torch.tensor(float(s_bulk), dtype=torch.float64, requires_grad=True)
+    sg = torch.tensor(float(s_ghost), dtype=torch.float64, requires_grad=True)
+    rho0 = torch.as_tensor(rho0, dtype=torch.float64).clone().requires_grad_(True)
+    loss = rmin_after(rho0, G, tau, steps, rho_v, rho_l, collision="mrt", s_bulk=sb, s_ghost=sg,
+                      segment=segment)
+    loss.backward()
+    return float(loss.detach()), float(sb.grad), float(sg.grad)

@@ -51,7 +51,9 @@ struct AdjWork {
   char* R[2] = {nullptr, nullptr};
   char* fbar = nullptr;  // 3 n values
   double* partial = nullptr;
-  double* acc = nullptr;  // dL/dG, dL/dtau
+  double* acc = nullptr;  // dL/dG, dL/dtau, dL/ds_bulk, dL/ds_ghost
+  double rates[2] = {0.0, 0.0};  // dL/ds_bulk, dL/ds_ghost of the last backward pass
+  bool have_rates = false;
 };
 
 }  // namespace
@@ -573,7 +575,7 @@ AdjLayout adj_layout(const lbsc_params& p, int64_t nsteps, int32_t segment) {
   L.P = 2 * L.lat;
   L.R = 2 * L.rho;
   L.fbar = align_up(3 * (size_t)a.n * elem_size(p));
-  L.partial = align_up(2 * sizeof(double) * (size_t)lbsc::adj_blocks(a));
+  L.partial = align_up(4 * sizeof(double) * (size_t)lbsc::adj_blocks(a));
   L.acc = kAlign;
   L.total = L.cp + L.ring + L.rhos + L.P + L.R + L.fbar + L.partial + L.acc;
   return L;
@@ -859,7 +861,8 @@ int lbsc_adjoint_backward(lbsc_ctx* c, const double* rhobar_dev, double* rho0bar
   g.a = mm.a;
   g.fbar = w.fbar;
   g.partial = w.partial;
-  HIP_OR_FAIL(c, hipMemsetAsync(w.acc, 0, 2 * sizeof(double), c->stream));
+  w.have_rates = false;
+  HIP_OR_FAIL(c, hipMemsetAsync(w.acc, 0, 4 * sizeof(double), c->stream));
   int pc = 0;  // adjoint state of the step after the one being processed
   g.p_out = w.P[pc];
   g.r_out = w.R[pc];
@@ -892,11 +895,22 @@ int lbsc_adjoint_backward(lbsc_ctx* c, const double* rhobar_dev, double* rho0bar
   g.p_next = w.P[pc];
   g.r_next = w.R[pc];
   HIP_OR_FAIL(c, lbsc::launch_adjoint_final(prec, g, rho0bar_dev, c->stream));
-  double acc[2];
+  double acc[4];
   HIP_OR_FAIL(c, hipMemcpyAsync(acc, w.acc, sizeof(acc), hipMemcpyDeviceToHost, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   if (dL_dG) *dL_dG = acc[0];
   if (dL_dtau) *dL_dtau = acc[1];
+  w.rates[0] = acc[2];
+  w.rates[1] = acc[3];
+  w.have_rates = true;
+  return LBSC_OK;
+}
+
+int lbsc_adjoint_rate_gradients(const lbsc_ctx* c, double* dL_ds_bulk, double* dL_ds_ghost) {
+  if (!c) return LBSC_EINVAL;
+  if (!c->adj.have_rates) return LBSC_ESTATE;
+  if (dL_ds_bulk) *dL_ds_bulk = c->adj.rates[0];
+  if (dL_ds_ghost) *dL_ds_ghost = c->adj.rates[1];
   return LBSC_OK;
 }
 

@@ -859,24 +859,8 @@ int grid_for(long long n, int threads) {
 // Kernel A takes (P, r) of step n+1, forms dL/dB_n at every node, runs the
 // collision backwards and writes P of step n and dL/dF; kernel B turns dL/dF
 // into r of step n with the transposed force stencil.  Parameter gradients
-// (dL/dG, dL/dtau) are accumulated per block in float64.
-
-__device__ inline double block_sum2(double v0, double v1, double* out) {
-  __shared__ double red[4][2];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  v0 = wave_sum(v0);
-  v1 = wave_sum(v1);
-  if (lane == 0) {
-    red[wv][0] = v0;
-    red[wv][1] = v1;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    out[0] = red[0][0] + red[1][0] + red[2][0] + red[3][0];
-    out[1] = red[0][1] + red[1][1] + red[2][1] + red[3][1];
-  }
-  return 0.0;
-}
+// (dL/dG, dL/dtau and, for MRT, dL/ds_bulk, dL/ds_ghost) are accumulated per
+// block in float64.
 
 template <class T, int COLL>
 __global__ void __launch_bounds__(256) k_adj_collide(AdjArgs g) {
@@ -890,7 +874,7 @@ __global__ void __launch_bounds__(256) k_adj_collide(AdjArgs g) {
   T* __restrict__ po = (T*)g.p_out;
   T* __restrict__ fb = (T*)g.fbar;
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  double dG = 0.0, dtau = 0.0;
+  double dG = 0.0, dtau = 0.0, dbulk = 0.0, dghost = 0.0;
   if (i < a.n) {
     const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / a.plane);
     const Nbr nb = neighbours(x, y, z, a.nx, a.ny, a.nz, a.plane);
@@ -986,7 +970,7 @@ __global__ void __launch_bounds__(256) k_adj_collide(AdjArgs g) {
       meq[15] = rr * ux * uz;                  msrc[15] = ux * Fz + uz * Fx;
       // kb_i = -sum_a M_ia gb_a; m_i = sum_b M_ib f_b
       R mb[Q], eqb[Q], srb[Q];
-      R dlam = R(0);
+      R dlam = R(0), dlb = R(0), dlg = R(0);
       static_for<Q>([&](auto ic) {
         constexpr int ii = decltype(ic)::value;
         mb[ii] = R(0);
@@ -1007,11 +991,16 @@ __global__ void __launch_bounds__(256) k_adj_collide(AdjArgs g) {
           mb[ii] = kb * lam * inv_d;
           eqb[ii] = -kb * lam * inv_d;
           srb[ii] = -kb * (R(1) - R(0.5) * lam) * inv_d;
-          if constexpr (mrt_class(ii) == 2)
-            dlam += kb * (m - meq[ii] + R(0.5) * msrc[ii]) * inv_d;
+          // dm*_i / ds_i = -(m_i - meq_i) - msrc_i / 2, and dL/dm*_i = -kb_i / d_i.
+          const R dls = kb * (m - meq[ii] + R(0.5) * msrc[ii]) * inv_d;
+          if constexpr (mrt_class(ii) == 1) dlb += dls;
+          if constexpr (mrt_class(ii) == 2) dlam += dls;
+          if constexpr (mrt_class(ii) == 3) dlg += dls;
         }
       });
       dtau = -double(dlam) / (double(ph.tau) * double(ph.tau));
+      dbulk = double(dlb);
+      dghost = double(dlg);
       // F from the conserved momentum rows (D_a += 0.1 c_a . F)
       static_for<Q>([&](auto ac) {
         constexpr int q = decltype(ac)::value;
@@ -1096,7 +1085,8 @@ __global__ void __launch_bounds__(256) k_adj_collide(AdjArgs g) {
     if (a.G != 0.0)
       dG = (double(Fbx) * double(Fx) + double(Fby) * double(Fy) + double(Fbz) * double(Fz)) / a.G;
   }
-  block_sum2(dG, dtau, g.partial + 2LL * blockIdx.x);
+  double v[4] = {dG, dtau, dbulk, dghost};
+  block_sums<4>(v, g.partial + 4LL * blockIdx.x);
 }
 
 // r(x) = psi'(rho(x)) * dL/dpsi(x), with
@@ -1165,20 +1155,21 @@ __global__ void __launch_bounds__(256) k_adj_final(AdjArgs g, double* __restrict
   }
 }
 
-// acc[0..1] += sum of nb block partials, in a fixed order.
+// acc[0..3] += sum of nb block partials (dL/dG, dL/dtau, dL/ds_bulk,
+// dL/ds_ghost), in a fixed order.
 __global__ void __launch_bounds__(256) k_adj_reduce(const double* __restrict__ part, int nb,
                                                     double* __restrict__ acc) {
-  double v0 = 0.0, v1 = 0.0;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nb; b += 256) {
-    v0 += part[2LL * b];
-    v1 += part[2LL * b + 1];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] += part[4LL * b + k];
   }
-  __shared__ double tot[2];
-  block_sum2(v0, v1, tot);
+  __shared__ double tot[4];
+  block_sums<4>(v, tot);
   __syncthreads();
   if (threadIdx.x == 0) {
-    acc[0] += tot[0];
-    acc[1] += tot[1];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += tot[k];
   }
 }
 

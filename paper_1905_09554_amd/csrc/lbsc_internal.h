@@ -51,7 +51,8 @@ struct BatchLaunch {
 
 // One adjoint step (see the adjoint section of lbsc_device.hip): lattice
 // B_{n-1}, density rho_n, adjoint (P, r) of step n+1 in, of step n out,
-// dL/dF scratch (3n values) and per-block partials (2 doubles per block).
+// dL/dF scratch (3n values) and per-block partials (4 doubles per block:
+// dL/dG, dL/dtau, dL/ds_bulk, dL/ds_ghost).
 struct AdjArgs {
   StepArgs a;
   const void* bprev;

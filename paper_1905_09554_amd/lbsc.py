@@ -88,6 +88,7 @@ def library():
             "lbsc_adjoint_forward": (ctypes.c_int, [vp, i64, i32, vp, sz]),
             "lbsc_rmin_gradient": (ctypes.c_int, [vp, dbl, dbl, vp, P(dbl)]),
             "lbsc_adjoint_backward": (ctypes.c_int, [vp, vp, vp, P(dbl), P(dbl)]),
+            "lbsc_adjoint_rate_gradients": (ctypes.c_int, [vp, P(dbl), P(dbl)]),
             "lbsc_batch_state_bytes": (sz, [i32, P(Params)]),
             "lbsc_init_batch": (ctypes.c_int, [P(vp), i32, P(Params), P(P(dbl)), vp, sz, vp]),
             "lbsc_batch_size": (i32, [vp]),
@@ -261,6 +262,13 @@ class Simulation:
                                                ctypes.c_void_p(out.data_ptr()), ctypes.byref(dG),
                                                ctypes.byref(dtau)), self._ctx)
         return out, dG.value, dtau.value
+
+    def rate_gradients(self):
+        """(dL/ds_bulk, dL/ds_ghost) of the last adjoint_backward (MRT; 0 for BGK)."""
+        b, g = ctypes.c_double(), ctypes.c_double()
+        _check(library().lbsc_adjoint_rate_gradients(self._ctx, ctypes.byref(b),
+                                                     ctypes.byref(g)), self._ctx)
+        return b.value, g.value
 
     # -- launch shape
     def set_tuning(self, threads=0, z_chunk=0, xcd_remap=1, block_y=0, pop_pad=-1,

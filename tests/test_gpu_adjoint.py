@@ -2,8 +2,8 @@
 gradient and against central finite differences of the GPU forward run.
 
 Loss: minimum ligament radius after the run (Sec. 4, Fig. 5).  Gradients with
-respect to G, tau, the initial density, and through torch to the Fourier
-amplitudes of the initial radius.
+respect to G, tau, the MRT bulk and ghost rates, the initial density, and
+through torch to the Fourier amplitudes of the initial radius.
 """
 import math
 
@@ -18,7 +18,7 @@ from tests import gpu_cases as gc
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_grads(rho0, G, tau, steps, segment, coll, prec, rv, rl):
+def _gpu_grads(rho0, G, tau, steps, segment, coll, prec, rv, rl, rates=False):
     from paper_1905_09554_amd import lbsc
     nz, ny, nx = rho0.shape
     prm = lbsc.make_params(nx, ny, nz, collision=coll, precision=prec, G=G, tau=tau)
@@ -27,14 +27,17 @@ def _gpu_grads(rho0, G, tau, steps, segment, coll, prec, rv, rl):
     rhobar, rmin = sim.rmin_gradient(rv, rl)
     g_rho, g_G, g_tau = sim.adjoint_backward(rhobar)
     out = (rmin, g_rho.cpu().numpy(), g_G, g_tau)
+    if rates:
+        out = out + sim.rate_gradients()
     sim.close()
     return out
 
 
-def _rmin(rho0, G, tau, steps, coll, prec, rv, rl):
+def _rmin(rho0, G, tau, steps, coll, prec, rv, rl, s_bulk=1.0, s_ghost=1.2):
     from paper_1905_09554_amd import lbsc
     nz, ny, nx = rho0.shape
-    prm = lbsc.make_params(nx, ny, nz, collision=coll, precision=prec, G=G, tau=tau)
+    prm = lbsc.make_params(nx, ny, nz, collision=coll, precision=prec, G=G, tau=tau,
+                           s_bulk=s_bulk, s_ghost=s_ghost)
     sim = lbsc.Simulation(rho0, prm)
     sim.step(steps)
     r = sim.diagnostics(rv, rl)["r_min"]
@@ -59,6 +62,24 @@ def test_adjoint_matches_oracle_autograd(coll):
     assert float(np.abs(g_rho - o_rho).max()) <= 1e-9 * float(np.abs(o_rho).max())
 
 
+def test_mrt_rate_gradients_match_oracle_autograd():
+    """dL/ds_bulk and dL/ds_ghost of the MRT adjoint against the oracle's
+    autograd (itself pinned to finite differences); BGK reports zeros."""
+    rv, rl = lbm_inputs.coexistence(-5.0)
+    rho0 = lbm_inputs.ligament_density(16, 16, 40, 4.5, 0.1, 1, rv, rl, noise=1e-3, seed=3)
+    steps, seg = 60, 16
+    out = _gpu_grads(rho0, -5.0, 0.9, steps, seg, "mrt", "f64", rv, rl, rates=True)
+    g_b, g_g = out[4], out[5]
+    o_rmin, o_b, o_g = oadj.rmin_rate_gradients(torch.from_numpy(rho0), -5.0, 0.9, steps, rv,
+                                                rl, 1.0, 1.2, segment=20)
+    print("ds_bulk %.8e (oracle %.8e)  ds_ghost %.8e (oracle %.8e)" % (g_b, o_b, g_g, o_g),
+          flush=True)
+    assert abs(out[0] - o_rmin) < 1e-12
+    assert abs(g_b - o_b) <= 1e-9 * abs(o_b) and abs(g_g - o_g) <= 1e-9 * abs(o_g)
+    bgk = _gpu_grads(rho0, -5.0, 0.9, steps, seg, "bgk", "f64", rv, rl, rates=True)
+    assert bgk[4] == 0.0 and bgk[5] == 0.0
+
+
 def _fourier_case(nx, ny, nz, R, nmodes, seed):
     rv, rl = lbm_inputs.coexistence(-5.0)
     amps = lbm_inputs.fourier_amplitudes(nmodes, R, 0.02, seed)
@@ -80,20 +101,25 @@ def test_adjoint_matches_central_differences(prec, tol):
     a = torch.tensor(amps, dtype=torch.float64, requires_grad=True)
     G = torch.tensor(-5.0, dtype=torch.float64, requires_grad=True)
     tau = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    sb = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    sg = torch.tensor(1.2, dtype=torch.float64, requires_grad=True)
     r = lbm_inputs.fourier_radius_torch(nz, R, a)
     rho0 = lbm_inputs.density_from_radius_torch(nx, ny, r, rv, rl)
-    loss = lag.ligament_rmin(rho0, G, tau, cfg)
+    loss = lag.ligament_rmin(rho0, G, tau, cfg, s_bulk=sb, s_ghost=sg)
     loss.backward()
     h = 1e-4
 
-    def L(am=amps, Gv=-5.0, tv=1.0):
+    def L(am=amps, Gv=-5.0, tv=1.0, bv=1.0, gv=1.2):
         # Finite differences in float64 whatever the adjoint's precision.
         return _rmin(_rho_from_amps(am, nx, ny, nz, R, rv, rl), Gv, tv, steps, "mrt", "f64",
-                     rv, rl)
+                     rv, rl, s_bulk=bv, s_ghost=gv)
 
     fd = {"G": (L(Gv=-5.0 + h) - L(Gv=-5.0 - h)) / (2 * h),
-          "tau": (L(tv=1.0 + h) - L(tv=1.0 - h)) / (2 * h)}
-    ad = {"G": float(G.grad), "tau": float(tau.grad)}
+          "tau": (L(tv=1.0 + h) - L(tv=1.0 - h)) / (2 * h),
+          "s_bulk": (L(bv=1.0 + h) - L(bv=1.0 - h)) / (2 * h),
+          "s_ghost": (L(gv=1.2 + h) - L(gv=1.2 - h)) / (2 * h)}
+    ad = {"G": float(G.grad), "tau": float(tau.grad), "s_bulk": float(sb.grad),
+          "s_ghost": float(sg.grad)}
     for m in (0, 1, 5):
         e = np.zeros_like(amps)
         e[m] = h

@@ -39,3 +39,23 @@ def test_autograd_matches_finite_differences():
         ad_d = float((g_rho * d).sum())
         assert abs(ad_d - fd_d) <= 1e-5 * abs(fd_d) + 1e-9, (coll, ad_d, fd_d)
         assert np.isfinite(loss)
+
+
+def test_rate_gradients_match_finite_differences():
+    rho0, rv, rl = _case()
+    steps = 30
+    loss, g_b, g_g = adjoint.rmin_rate_gradients(rho0, -5.0, 0.9, steps, rv, rl, 1.1, 1.2,
+                                                 segment=10)
+    h = 1e-5
+
+    def L(sb=1.1, sg=1.2):
+        with torch.no_grad():
+            return float(adjoint.rmin_after(rho0, -5.0, 0.9, steps, rv, rl, collision="mrt",
+                                            s_bulk=sb, s_ghost=sg))
+
+    fd_b = (L(sb=1.1 + h) - L(sb=1.1 - h)) / (2 * h)
+    fd_g = (L(sg=1.2 + h) - L(sg=1.2 - h)) / (2 * h)
+    assert abs(g_b - fd_b) <= 1e-5 * abs(fd_b) + 1e-9, (g_b, fd_b)
+    assert abs(g_g - fd_g) <= 1e-5 * abs(fd_g) + 1e-9, (g_g, fd_g)
+    # both rates matter to this loss
+    assert abs(fd_b) > 1e-6 and abs(fd_g) > 1e-6
