@@ -165,11 +165,15 @@ WORKLOADS = {
 }
 
 
-def workload_density(name, seed=None):
-    """Initial density of a single-ligament workload; returns (rho0, info)."""
+def workload_density(name, seed=None, kR=None):
+    """Initial density of a single-ligament workload; returns (rho0, info).
+    kR overrides the workload's wavenumber (the 256 x 256 x 1024 box is
+    specified for kR in {0.45, 0.7})."""
     w = dict(WORKLOADS[name])
     if seed is not None:
         w["seed"] = seed
+    if kR is not None:
+        w["kR"] = kR
     rho_v, rho_l = coexistence(w["G"])
     if "nmodes" in w:
         amps = fourier_amplitudes(w["nmodes"], w["R"], w["rel_std"], w["seed"])

@@ -26,16 +26,18 @@ def _sample_nodes(shape, tune, rng, count=24):
     return out
 
 
-@pytest.mark.parametrize("name,coll,prec,steps", [
-    ("ligament_256x256x1024_mrt_f32", "mrt", "f32", 2),
-    ("ligament_128x128x512", "bgk", "f64", 2),
-    ("ligament_128x128x512", "mrt", "f32", 3),
+@pytest.mark.parametrize("name,coll,prec,steps,kR", [
+    ("ligament_256x256x1024_mrt_f32", "mrt", "f32", 2, None),
+    ("ligament_256x256x1024_mrt_f32", "mrt", "f64", 2, 0.45),
+    ("ligament_128x128x512", "bgk", "f64", 2, None),
+    ("ligament_128x128x512", "mrt", "f32", 3, None),
 ])
-def test_full_size_sampled(name, coll, prec, steps):
+def test_full_size_sampled(name, coll, prec, steps, kR):
     from paper_1905_09554_amd import lbsc, tuning
-    rho0, info = lbm_inputs.workload_density(name)
+    rho0, info = lbm_inputs.workload_density(name, kR=kR)
     nz, ny, nx = rho0.shape
-    print("full size %s %s %s: %d nodes" % (name, coll, prec, rho0.size), flush=True)
+    print("full size %s %s %s kR_eff %.4f: %d nodes" % (name, coll, prec, info["kR_eff"],
+                                                       rho0.size), flush=True)
     prm = lbsc.make_params(nx, ny, nz, collision=coll, precision=prec, G=info["G"],
                            tau=info["tau"])
     sim = lbsc.Simulation(rho0, prm)
