@@ -485,8 +485,9 @@ int step_batch(lbsc_ctx* c, int64_t nsteps) {
 
 int moments_of(lbsc_ctx* c, Member* mm, double* rho_dev, double* u_dev, double* p_dev) {
   if (!rho_dev) return fail(&c->err, LBSC_EINVAL, "rho_dev is required");
+  // The idle lattice (19 n storage values >= n doubles) holds psi.
   hipError_t e = lbsc::launch_moments(mm->p.precision, mm->lat[c->cur], rho_dev, u_dev, p_dev,
-                                      mm->a, c->stream);
+                                      (double*)mm->lat[c->cur ^ 1], mm->a, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "moments launch");
   return LBSC_OK;
 }

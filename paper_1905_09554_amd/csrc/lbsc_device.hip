@@ -653,7 +653,7 @@ k_scatter(const T* __restrict__ in, long long ps_in, T* __restrict__ lat, long l
 template <class T>
 __global__ void __launch_bounds__(256)
 k_moments1(const T* __restrict__ lat, double* __restrict__ rho, double* __restrict__ u,
-           StepArgs a) {
+           double* __restrict__ psi, StepArgs a) {
   const long long n = a.n;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -671,7 +671,9 @@ k_moments1(const T* __restrict__ lat, double* __restrict__ rho, double* __restri
       if (CY[q] != 0) jy += CY[q] * f[q];
       if (CZ[q] != 0) jz += CZ[q] * f[q];
     }
-    rho[i] = a.rho_ref + s;
+    const double r = a.rho_ref + s;
+    rho[i] = r;
+    psi[i] = psi_of(r, a.psi_rho0, 1.0 / a.psi_rho0);
     if (u) {
       u[i] = jx;
       u[n + i] = jy;
@@ -680,21 +682,21 @@ k_moments1(const T* __restrict__ lat, double* __restrict__ rho, double* __restri
   }
 }
 
-// Shan-Chen force of node (x, y, z) from a float64 density field.
-__device__ inline void force_from_rho(const double* __restrict__ rho, const Nbr& b,
+// Shan-Chen force of node (x, y, z) from a float64 field of psi (computed
+// once per node by the pass that wrote rho).
+__device__ inline void force_from_psi(const double* __restrict__ psi, const Nbr& b,
                                       const StepArgs& a, double& Fx, double& Fy, double& Fz,
                                       double& psi_c) {
-  const double r0 = a.psi_rho0, ir0 = 1.0 / a.psi_rho0;
   double sx = 0, sy = 0, sz = 0;
 #pragma unroll
   for (int q = 1; q < Q; ++q) {
     const unsigned idx = b.zo[1 + CZ[q]] + b.yo[1 + CY[q]] + b.xo[1 + CX[q]];
-    const double wp = weight<double>(q) * psi_of(rho[idx], r0, ir0);
+    const double wp = weight<double>(q) * psi[idx];
     if (CX[q] != 0) sx += CX[q] * wp;
     if (CY[q] != 0) sy += CY[q] * wp;
     if (CZ[q] != 0) sz += CZ[q] * wp;
   }
-  psi_c = psi_of(rho[b.zo[1] + b.yo[1] + b.xo[1]], r0, ir0);
+  psi_c = psi[b.zo[1] + b.yo[1] + b.xo[1]];
   Fx = -a.G * psi_c * sx;
   Fy = -a.G * psi_c * sy;
   Fz = -a.G * psi_c * sz;
@@ -702,8 +704,8 @@ __device__ inline void force_from_rho(const double* __restrict__ rho, const Nbr&
 
 // Pass 2: u^b = (j + F/2)/rho and the pressure of Eq. EOS_SC.
 __global__ void __launch_bounds__(256)
-k_moments2(const double* __restrict__ rho, double* __restrict__ u, double* __restrict__ p,
-           StepArgs a) {
+k_moments2(const double* __restrict__ rho, const double* __restrict__ psi_f,
+           double* __restrict__ u, double* __restrict__ p, StepArgs a) {
   const long long n = a.n;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -712,7 +714,7 @@ k_moments2(const double* __restrict__ rho, double* __restrict__ u, double* __res
     const int z = (int)(i / a.plane);
     const Nbr nb = neighbours(x, y, z, a.nx, a.ny, a.nz, a.plane);
     double Fx, Fy, Fz, psi;
-    force_from_rho(rho, nb, a, Fx, Fy, Fz, psi);
+    force_from_psi(psi_f, nb, a, Fx, Fy, Fz, psi);
     const double r = rho[i];
     if (u) {
       u[i] = (u[i] + 0.5 * Fx) / r;
@@ -782,6 +784,7 @@ k_diag1(const T* __restrict__ lat, double* __restrict__ rho, double* __restrict_
     }
     const double r = a.rho_ref + s;
     rho[(long long)z * a.plane + i] = r;
+    rho[a.n + (long long)z * a.plane + i] = psi_of(r, a.psi_rho0, 1.0 / a.psi_rho0);
     v[0] += r;
     v[1] += jx;
     v[2] += jy;
@@ -802,7 +805,7 @@ k_diag2(const double* __restrict__ rho, double* __restrict__ part, StepArgs a,
     const int x = i % a.nx, y = i / a.nx;
     const Nbr nb = neighbours(x, y, z, a.nx, a.ny, a.nz, a.plane);
     double Fx, Fy, Fz, psi;
-    force_from_rho(rho, nb, a, Fx, Fy, Fz, psi);
+    force_from_psi(rho + a.n, nb, a, Fx, Fy, Fz, psi);
     v[0] += Fx;
     v[1] += Fy;
     v[2] += Fz;
@@ -1293,16 +1296,19 @@ hipError_t launch_batch(const BatchLaunch& L, hipStream_t s) {
 }
 
 hipError_t launch_moments(int prec, const void* lat, double* rho, double* u, double* p,
-                          const StepArgs& a, hipStream_t s) {
+                          double* psi_scratch, const StepArgs& a, hipStream_t s) {
   const int g = grid_for(a.n, 256);
   if (prec == 0)
-    hipLaunchKernelGGL(k_moments1<double>, dim3(g), dim3(256), 0, s, (const double*)lat, rho, u, a);
+    hipLaunchKernelGGL(k_moments1<double>, dim3(g), dim3(256), 0, s, (const double*)lat, rho, u,
+                       psi_scratch, a);
   else
-    hipLaunchKernelGGL(k_moments1<float>, dim3(g), dim3(256), 0, s, (const float*)lat, rho, u, a);
+    hipLaunchKernelGGL(k_moments1<float>, dim3(g), dim3(256), 0, s, (const float*)lat, rho, u,
+                       psi_scratch, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (u || p) {
-    hipLaunchKernelGGL(k_moments2, dim3(g), dim3(256), 0, s, (const double*)rho, u, p, a);
+    hipLaunchKernelGGL(k_moments2, dim3(g), dim3(256), 0, s, (const double*)rho,
+                       (const double*)psi_scratch, u, p, a);
     e = hipGetLastError();
   }
   return e;

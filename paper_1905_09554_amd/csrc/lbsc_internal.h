@@ -74,9 +74,11 @@ hipError_t launch_init(int prec, void* lat, const double* rho0_dev, const StepAr
 hipError_t launch_step(int prec, int coll, int forc, int threads, int npt, const void* src,
                        void* dst, const StepArgs& a, hipStream_t s);
 hipError_t launch_batch(const BatchLaunch& L, hipStream_t s);
+// psi_scratch: n doubles of device scratch (the idle lattice) for psi(rho).
 hipError_t launch_moments(int prec, const void* lat, double* rho, double* u, double* p,
-                          const StepArgs& a, hipStream_t s);
-// Diagnostics: partials holds diag_blocks(a) * 8 doubles; out holds 4 + nz.
+                          double* psi_scratch, const StepArgs& a, hipStream_t s);
+// Diagnostics: rho_scratch holds 2 n doubles (rho, then psi); partials holds
+// diag_blocks(a) * 8 doubles; out holds 4 + nz.
 int diag_blocks(const StepArgs& a);
 hipError_t launch_diagnostics(int prec, const void* lat, double* rho_scratch, double* partials,
                               double* out, double rho_v, double rho_l, const StepArgs& a,
