@@ -168,9 +168,15 @@ class Simulation:
 
     # -- lifecycle
     def close(self):
+        """Destroys the context and releases the device buffer (once the
+        stream has finished with it)."""
         if getattr(self, "_ctx", None):
             library().lbsc_destroy(self._ctx)
             self._ctx = None
+        if getattr(self, "_buf", None) is not None:
+            self.stream.synchronize()
+            self._buf = None
+            self._ws = None
 
     def __del__(self):
         try:
@@ -326,9 +332,14 @@ class Batch:
         self.size = n
 
     def close(self):
+        """Destroys the context and releases the device buffer (once the
+        stream has finished with it)."""
         if getattr(self, "_ctx", None):
             library().lbsc_destroy(self._ctx)
             self._ctx = None
+        if getattr(self, "_buf", None) is not None:
+            self.stream.synchronize()
+            self._buf = None
 
     def __del__(self):
         try:
