@@ -108,3 +108,30 @@ def test_dispersion_batch_full_size_sampled():
         del rho, u
     b.close()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("tuning", [None, dict(threads=1024), dict(threads=256, block_x=64),
+                                    dict(threads=1024, block_x=128, persistent=1)])
+def test_batch_wide_and_narrow_members_bitwise(tuning):
+    """Members whose rows are wider than a work-group (split into x tiles,
+    ragged last tile) next to narrow ones, against single runs."""
+    from paper_1905_09554_amd import lbsc
+    rv, rl = lbm_inputs.coexistence(-5.0)
+    specs = [(1100, 3, 4), (300, 6, 8), (40, 40, 12)]
+    rhos, params = [], []
+    for nx, ny, nz in specs:
+        g_ = np.random.default_rng(nx)
+        rhos.append(rv + (rl - rv) * g_.random((nz, ny, nx)))
+        params.append(lbsc.make_params(nx, ny, nz, collision="mrt", precision="f32", G=-5.0,
+                                       tau=0.9))
+    b = lbsc.Batch(rhos, params)
+    if tuning:
+        b.set_tuning(**tuning)
+    b.step(9)
+    for i, (r, p) in enumerate(zip(rhos, params)):
+        sim = lbsc.Simulation(r, p)
+        sim.step(9)
+        single, _ = sim.get_state()
+        sim.close()
+        assert np.array_equal(b.get_state(i), single), (i, tuning)
+    b.close()
