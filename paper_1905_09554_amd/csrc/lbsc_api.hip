@@ -50,6 +50,7 @@ struct AdjWork {
   char* P[2] = {nullptr, nullptr};
   char* R[2] = {nullptr, nullptr};
   char* fbar = nullptr;  // 3 n values
+  char* psi = nullptr;   // n values
   double* partial = nullptr;
   double* acc = nullptr;  // dL/dG, dL/dtau, dL/ds_bulk, dL/ds_ghost
   double rates[2] = {0.0, 0.0};  // dL/ds_bulk, dL/ds_ghost of the last backward pass
@@ -559,7 +560,7 @@ int set_state_of(lbsc_ctx* c, Member* mm, const void* host, size_t bytes) {
 // Workspace layout of the adjoint for a single box (lattices sized for the
 // largest padding so any tuning of the box fits).
 struct AdjLayout {
-  size_t lat, rho, cp, ring, rhos, P, R, fbar, partial, acc, total;
+  size_t lat, rho, cp, ring, rhos, P, R, fbar, psi, partial, acc, total;
   int ncp;
 };
 
@@ -576,9 +577,10 @@ AdjLayout adj_layout(const lbsc_params& p, int64_t nsteps, int32_t segment) {
   L.P = 2 * L.lat;
   L.R = 2 * L.rho;
   L.fbar = align_up(3 * (size_t)a.n * elem_size(p));
+  L.psi = align_up((size_t)a.n * elem_size(p));
   L.partial = align_up(4 * sizeof(double) * (size_t)lbsc::adj_blocks(a));
   L.acc = kAlign;
-  L.total = L.cp + L.ring + L.rhos + L.P + L.R + L.fbar + L.partial + L.acc;
+  L.total = L.cp + L.ring + L.rhos + L.P + L.R + L.fbar + L.psi + L.partial + L.acc;
   return L;
 }
 
@@ -814,6 +816,8 @@ int lbsc_adjoint_forward(lbsc_ctx* c, int64_t nsteps, int32_t segment, void* wor
   base += L.R;
   w.fbar = base;
   base += L.fbar;
+  w.psi = base;
+  base += L.psi;
   w.partial = (double*)base;
   base += L.partial;
   w.acc = (double*)base;
@@ -861,9 +865,12 @@ int lbsc_adjoint_backward(lbsc_ctx* c, const double* rhobar_dev, double* rho0bar
   lbsc::AdjArgs g;
   g.a = mm.a;
   g.fbar = w.fbar;
+  g.psi = w.psi;
   g.partial = w.partial;
   w.have_rates = false;
   HIP_OR_FAIL(c, hipMemsetAsync(w.acc, 0, 4 * sizeof(double), c->stream));
+  HIP_OR_FAIL(c, hipMemsetAsync(w.partial, 0, 4 * sizeof(double) * (size_t)lbsc::adj_blocks(mm.a),
+                                c->stream));
   int pc = 0;  // adjoint state of the step after the one being processed
   g.p_out = w.P[pc];
   g.r_out = w.R[pc];
@@ -889,13 +896,14 @@ int lbsc_adjoint_backward(lbsc_ctx* c, const double* rhobar_dev, double* rho0bar
       g.r_next = w.R[pc];
       g.p_out = w.P[pc ^ 1];
       g.r_out = w.R[pc ^ 1];
-      HIP_OR_FAIL(c, lbsc::launch_adjoint_step(prec, mm.p.collision, g, w.acc, c->stream));
+      HIP_OR_FAIL(c, lbsc::launch_adjoint_step(prec, mm.p.collision, g, c->stream));
       pc ^= 1;
     }
   }
   g.p_next = w.P[pc];
   g.r_next = w.R[pc];
   HIP_OR_FAIL(c, lbsc::launch_adjoint_final(prec, g, rho0bar_dev, c->stream));
+  HIP_OR_FAIL(c, lbsc::launch_adjoint_reduce(g, w.acc, c->stream));
   double acc[4];
   HIP_OR_FAIL(c, hipMemcpyAsync(acc, w.acc, sizeof(acc), hipMemcpyDeviceToHost, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));

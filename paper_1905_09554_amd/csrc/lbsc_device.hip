@@ -899,7 +899,9 @@ __global__ void __launch_bounds__(256) k_adj_collide(AdjArgs g) {
       if constexpr (CY[b] != 0) vy += R(CY[b]) * wp;
       if constexpr (CZ[b] != 0) vz += R(CZ[b]) * wp;
     });
-    const R gpsi = -ph.G * psi_of(R(rho[i]), ph.psi_rho0, ph.inv_psi_rho0);
+    const R psi_c = psi_of(R(rho[i]), ph.psi_rho0, ph.inv_psi_rho0);
+    static_cast<T*>(g.psi)[i] = T(psi_c);  // for the transposed stencil of kernel B
+    const R gpsi = -ph.G * psi_c;
     const R Fx = gpsi * vx, Fy = gpsi * vy, Fz = gpsi * vz;
     // Forward moments (as in the collision).
     R s = R(0), jx = R(0), jy = R(0), jz = R(0);
@@ -1088,8 +1090,16 @@ __global__ void __launch_bounds__(256) k_adj_collide(AdjArgs g) {
     if (a.G != 0.0)
       dG = (double(Fbx) * double(Fx) + double(Fby) * double(Fy) + double(Fbz) * double(Fz)) / a.G;
   }
+  // This block's partials accumulate over every step of the backward pass and
+  // are reduced once at its end (fixed order: steps, then blocks).
   double v[4] = {dG, dtau, dbulk, dghost};
-  block_sums<4>(v, g.partial + 4LL * blockIdx.x);
+  __shared__ double tot[4];
+  block_sums<4>(v, tot);
+  if (threadIdx.x == 0) {
+    double* pp = g.partial + 4LL * blockIdx.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pp[k] += tot[k];
+  }
 }
 
 // r(x) = psi'(rho(x)) * dL/dpsi(x), with
@@ -1101,6 +1111,7 @@ __global__ void __launch_bounds__(256) k_adj_psi(AdjArgs g) {
   const StepArgs& a = g.a;
   const Phys<R> ph = make_phys<R>(a);
   const T* __restrict__ rho = (const T*)g.rho;
+  const T* __restrict__ psi = (const T*)g.psi;
   const T* __restrict__ fb = (const T*)g.fbar;
   T* __restrict__ ro = (T*)g.r_out;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.n;
@@ -1113,8 +1124,8 @@ __global__ void __launch_bounds__(256) k_adj_psi(AdjArgs g) {
       constexpr int b = decltype(bc)::value + 1;
       const unsigned ip = nb.zo[1 + CZ[b]] + nb.yo[1 + CY[b]] + nb.xo[1 + CX[b]];
       const unsigned im = nb.zo[1 - CZ[b]] + nb.yo[1 - CY[b]] + nb.xo[1 - CX[b]];
-      const R wpp = weight<R>(b) * psi_of(R(rho[ip]), ph.psi_rho0, ph.inv_psi_rho0);
-      const R wpm = weight<R>(b) * psi_of(R(rho[im]), ph.psi_rho0, ph.inv_psi_rho0);
+      const R wpp = weight<R>(b) * R(psi[ip]);
+      const R wpm = weight<R>(b) * R(psi[im]);
       R cf = R(0), cfm = R(0);
       if constexpr (CX[b] != 0) { cf += R(CX[b]) * fx; cfm += R(CX[b]) * R(fb[im]); }
       if constexpr (CY[b] != 0) { cf += R(CY[b]) * fy; cfm += R(CY[b]) * R(fb[a.n + im]); }
@@ -1367,7 +1378,13 @@ hipError_t launch_scatter(int prec, const void* in, long long ps_in, void* lat, 
 
 int adj_blocks(const StepArgs& a) { return (int)((a.n + 255) / 256); }
 
-hipError_t launch_adjoint_step(int prec, int coll, const AdjArgs& g, double* acc, hipStream_t s) {
+hipError_t launch_adjoint_reduce(const AdjArgs& g, double* acc, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, s, (const double*)g.partial,
+                     adj_blocks(g.a), acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(int prec, int coll, const AdjArgs& g, hipStream_t s) {
   const int nb = adj_blocks(g.a);
   if (prec == 0) {
     if (coll == kMRT)
@@ -1381,9 +1398,6 @@ hipError_t launch_adjoint_step(int prec, int coll, const AdjArgs& g, double* acc
       hipLaunchKernelGGL((k_adj_collide<float, kBGK>), dim3(nb), dim3(256), 0, s, g);
   }
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, s, (const double*)g.partial, nb, acc);
-  e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int gp = grid_for(g.a.n, 256);
   if (prec == 0)

@@ -62,7 +62,8 @@ struct AdjArgs {
   void* p_out;
   void* r_out;
   void* fbar;
-  double* partial;
+  void* psi;        // psi(rho_n) of every node (n values), written by kernel A for kernel B
+  double* partial;  // accumulated over the whole backward pass, reduced once
 };
 
 enum Coll { kBGK = 0, kMRT = 1 };
@@ -94,7 +95,9 @@ hipError_t launch_scatter(int prec, const void* in, long long ps_in, void* lat, 
 // one backward step (acc[0..1] += dL/dG, dL/dtau of the step); the terminal
 // seed; dL/drho0 from the adjoint of step 0; the minimum-radius gradient.
 int adj_blocks(const StepArgs& a);
-hipError_t launch_adjoint_step(int prec, int coll, const AdjArgs& g, double* acc, hipStream_t s);
+hipError_t launch_adjoint_step(int prec, int coll, const AdjArgs& g, hipStream_t s);
+// acc[0..3] += the sums of the accumulated block partials.
+hipError_t launch_adjoint_reduce(const AdjArgs& g, double* acc, hipStream_t s);
 hipError_t launch_adjoint_seed(int prec, const AdjArgs& g, const double* rhobar, hipStream_t s);
 hipError_t launch_adjoint_final(int prec, const AdjArgs& g, double* rho0bar, hipStream_t s);
 hipError_t launch_rmin_grad(double* rho, const StepArgs& a, int zstar, double coef, double rho_v,

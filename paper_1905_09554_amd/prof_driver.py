@@ -5,7 +5,9 @@ counters).
 
 Runs the benchmark box (256 x 256 x 1024 ligament, MRT, the launch shape the
 benchmark uses) for a few steps, then a plain device-to-device copy of a known
-size whose counters calibrate FETCH_SIZE and WRITE_SIZE.
+size whose counters calibrate FETCH_SIZE and WRITE_SIZE.  With --adjoint it
+runs the adjoint workload instead (64 x 64 x 256 MRT, 4000 steps, checkpoints
+every 200, loss r_min): forward, loss gradient and backward, once.
 """
 import argparse
 import os
@@ -23,11 +25,28 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--adjoint", action="store_true",
+                    help="run the adjoint workload (forward with checkpoints, backward) instead")
     args = ap.parse_args()
 
     import torch
     import lbm_inputs
     from paper_1905_09554_amd import lbsc, tuning
+
+    if args.adjoint:
+        name = "adjoint_64x64x256_mrt_f32"
+        rho0, info = lbm_inputs.workload_density(name)
+        nz, ny, nx = rho0.shape
+        prm = lbsc.make_params(nx, ny, nz, collision=info["collision"], precision=args.precision,
+                               G=info["G"], tau=info["tau"])
+        sim = lbsc.Simulation(rho0, prm)
+        sim.adjoint_forward(info["steps"], info["checkpoint_every"])
+        rhobar, rmin = sim.rmin_gradient(info["rho_v"], info["rho_l"])
+        _, dG, dtau = sim.adjoint_backward(rhobar)
+        torch.cuda.synchronize()
+        print("adjoint done", name, args.precision, rmin, dG, dtau, flush=True)
+        sim.close()
+        return
 
     rho0, info = lbm_inputs.workload_density(args.workload)
     nz, ny, nx = rho0.shape
