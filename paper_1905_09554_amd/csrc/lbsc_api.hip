@@ -232,18 +232,24 @@ lbsc_tuning default_tuning(const lbsc_params* p, int32_t n) {
   // float64 (about 200 VGPRs, 2 waves per SIMD): 256-thread groups, two per
   // CU, so one group's loads overlap the other's collision.  float32 (about
   // 110 VGPRs): 512-thread groups, two per CU; boxes with rows of at most 256
-  // nodes and enough tiles run 1024-thread groups of whole rows four or more
-  // deep instead, one per CU (measured: 32.0 against 29.3 GLUPS on
-  // 256 x 256 x 1024, 29.9 against 27.9 on 128 x 128 x 512, 27.5 against
-  // 26.1 on the 64-ligament batch): the deeper tile's smaller halo ring
-  // outweighs the lost overlap.
+  // nodes and at least 256 tiles run 1024-thread groups of whole rows four or
+  // more deep instead, one per CU (measured: 32.0 against 29.3 GLUPS on
+  // 256 x 256 x 1024, 29.9 against 27.9 on 128 x 128 x 512, 27.2 against
+  // 25.6 on 64 x 64 x 256, 27.5 against 26.1 on the 64-ligament batch): the
+  // deeper tile's smaller halo ring outweighs the lost overlap.
+  // Boxes too small to give 256 groups of 512 threads even with one-plane
+  // chunks take 256-thread groups instead (32 x 32 x 64: 8.5 against 9.4 us
+  // per step).
   int nx = 1;
   for (int32_t i = 0; i < n; ++i) nx = std::max(nx, p[i].nx);
   if (p[0].precision == LBSC_F64) {
     t.threads = 256;
-  } else {
+  } else if (4 * nx <= 1024 && tile_columns(p, n, 1024) >= 256) {
+    t.threads = 1024;
+  } else if (tile_columns(p, n, 512) >= 256) {
     t.threads = 512;
-    if (4 * nx <= 1024 && tile_columns(p, n, 1024) >= 256LL * 16) t.threads = 1024;
+  } else {
+    t.threads = 256;
   }
   // Chunk length.  A single box on 1024-thread groups: one wave of 256 groups,
   // one per CU (no tail), up to 256 planes.  Otherwise about 512 groups of 1
