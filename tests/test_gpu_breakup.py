@@ -81,3 +81,15 @@ def test_perturbation_sweep_against_linear_theory():
     print("R0=28 MRT: T(0.1) %.3f, T(0.05) %.3f, delay %.3f (linear theory %.3f)"
           % (t10, t05, delay, lsa), flush=True)
     assert 0.75 * lsa < delay < 1.1 * lsa
+
+
+@pytest.mark.parametrize("op", ["mrt", "srt"])
+def test_float32_and_float64_break_at_the_same_step(op):
+    """The paper's operators at R0 = 14 (Table 1-2 parameters): the FP32
+    shifted storage pinches off at the same sampled step as FP64, as the
+    R0 = 70 MRT runs do (31 150 steps in both)."""
+    from paper_1905_09554_amd import breakup
+    t32, s32, _ = breakup.break_time(14, op, precision="f32", every=5)
+    t64, s64, _ = breakup.break_time(14, op, precision="f64", every=5)
+    print("%s R0=14: f32 %d steps, f64 %d steps" % (op, s32, s64), flush=True)
+    assert abs(s32 - s64) <= 5
