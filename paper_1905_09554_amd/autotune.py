@@ -1,7 +1,8 @@
 """Launch-shape search for the fused step, written to tuning_cache.json.
 
-    python -m paper_1905_09554_amd.autotune [--workload NAME] [--precision f32,f64]
-                                            [--collision mrt] [--steps K]
+    python -m paper_1905_09554_amd.autotune [--workload NAME | --box NX,NY,NZ]
+                                            [--precision f32,f64] [--collision mrt]
+                                            [--steps K] [--out FILE]
 
 For one box (a workload of lbm_inputs.WORKLOADS), times the step over a grid
 of launch shapes: work-group size, nodes per thread, tile width (whole rows
@@ -53,12 +54,27 @@ def time_shape(sim, steps):
     return e0.elapsed_time(e1) / 1e3 / steps
 
 
-def tune(workload, precision, collision, steps=20, progress=True, out=None):
+def box_density(nx, ny, nz):
+    """A ligament of radius min(nx, ny) / 4 along z in an nx x ny x nz box
+    (G = -5 coexisting densities, one wavelength, amplitude 0.05), for
+    tuning boxes that are not one of the named workloads."""
+    import lbm_inputs
+    rv, rl = lbm_inputs.coexistence(-5.0)
+    R = min(nx, ny) / 4.0
+    rho0 = lbm_inputs.ligament_density(nx, ny, nz, R, 0.05, 1, rv, rl)
+    return rho0, {"G": -5.0, "tau": 1.0}
+
+
+def tune(workload, precision, collision, steps=20, progress=True, out=None, box=None):
     import torch
     import lbm_inputs
     from . import lbsc, tuning
 
-    rho0, info = lbm_inputs.workload_density(workload)
+    if box is not None:
+        rho0, info = box_density(*box)
+        workload = "box_%dx%dx%d" % box
+    else:
+        rho0, info = lbm_inputs.workload_density(workload)
     nz, ny, nx = rho0.shape
     n = rho0.size
     prm = lbsc.make_params(nx, ny, nz, collision=collision, precision=precision, G=info["G"],
@@ -114,10 +130,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--out", default=None,
                     help="cache file to update (default: the package's tuning_cache.json)")
+    ap.add_argument("--box", default=None,
+                    help="nx,ny,nz of a box to tune instead of a named workload")
     args = ap.parse_args()
+    box = tuple(int(v) for v in args.box.split(",")) if args.box else None
     for prec in args.precision.split(","):
-        e = tune(args.workload, prec, args.collision, args.steps, out=args.out)
-        print(json.dumps({"workload": args.workload, "precision": prec,
+        e = tune(args.workload, prec, args.collision, args.steps, out=args.out, box=box)
+        name = "box_%dx%dx%d" % box if box else args.workload
+        print(json.dumps({"workload": name, "precision": prec,
                           "collision": args.collision, "best": e["tuning"],
                           "mlups": round(e["mlups"], 1),
                           "default_mlups": round(e["default"]["mlups"], 1)}), flush=True)

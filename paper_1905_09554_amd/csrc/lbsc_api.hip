@@ -155,9 +155,12 @@ int check_batch(int32_t n, const lbsc_params* p, std::string* msg) {
 // min_rows of them and their two halo rows fit one round (2 nx <= threads);
 // else the widest multiple of 64 columns whose ring, 2 (bx + 2) + 2 by, fits
 // one round with by = cap / bx >= min_rows; else the same with two rows.
-// float64 tiles want four rows (measured: 64 x 4 beats whole rows two deep
-// at 256 threads), float32 two.  Four psi planes of (by + 2)(bx + 2) values
-// must fit the 160 KB of LDS of a CU.
+// float64 tiles, 1024-thread groups and rows wider than half the group
+// want four rows (measured: 64 x 4 beats whole rows two deep at 256
+// threads; on rows of 384-672 nodes 128 x 4 tiles of 512 threads reach
+// 26.5-28.4 GLUPS against 22.1-24 for 192 x 2), other float32 tiles two.
+// Four psi planes of (by + 2)(bx + 2) values must fit the 160 KB of LDS of a
+// CU.
 int default_block_x(int nx, long long cap, int threads, int min_rows) {
   for (int rows = min_rows; rows >= 2; rows /= 2) {
     if ((long long)rows * nx <= cap && 2LL * nx <= threads) return nx;
@@ -169,7 +172,8 @@ int default_block_x(int nx, long long cap, int threads, int min_rows) {
 
 void tile_shape(int nx, int ny, long long cap, int threads, int block_x, int block_y, size_t elem,
                 int* bx_out, int* by_out) {
-  int bx = block_x > 0 ? block_x : default_block_x(nx, cap, threads, elem == 8 ? 4 : 2);
+  const int min_rows = (elem == 8 || threads >= 1024 || 2LL * nx > cap) ? 4 : 2;
+  int bx = block_x > 0 ? block_x : default_block_x(nx, cap, threads, min_rows);
   if (bx > nx) bx = nx;
   if (bx > cap) bx = (int)cap;
   const int rows = (int)std::max(1LL, cap / bx);
@@ -233,10 +237,12 @@ lbsc_tuning default_tuning(const lbsc_params* p, int32_t n) {
   // CU, so one group's loads overlap the other's collision.  float32 (about
   // 110 VGPRs): 512-thread groups, two per CU; boxes with rows of at most 256
   // nodes and at least 256 tiles run 1024-thread groups of whole rows four or
-  // more deep instead, one per CU (measured: 32.0 against 29.3 GLUPS on
-  // 256 x 256 x 1024, 29.9 against 27.9 on 128 x 128 x 512, 27.2 against
-  // 25.6 on 64 x 64 x 256, 27.5 against 26.1 on the 64-ligament batch): the
-  // deeper tile's smaller halo ring outweighs the lost overlap.
+  // more deep instead, one per CU.  Measured: 32.0 against 29.3 GLUPS on
+  // 256 x 256 x 1024, 29.9 against 27.9 on 128 x 128 x 512, 27.2 against 25.6
+  // on 64 x 64 x 256, 27.5 against 26.1 on the 64-ligament batch: the deeper
+  // tile's smaller halo ring outweighs the lost overlap.  Wider rows split
+  // into tiles of whole 1024-thread groups lose (23.9 against 28.4 on
+  // 384 x 384 x 1024) and take 512 threads.
   // Boxes too small to give 256 groups of 512 threads even with one-plane
   // chunks take 256-thread groups instead (32 x 32 x 64: 8.5 against 9.4 us
   // per step).
