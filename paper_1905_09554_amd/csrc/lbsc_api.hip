@@ -158,7 +158,7 @@ int check_batch(int32_t n, const lbsc_params* p, std::string* msg) {
 // float64 tiles, 1024-thread groups and rows wider than half the group
 // want four rows (measured: 64 x 4 beats whole rows two deep at 256
 // threads; on rows of 384-672 nodes 128 x 4 tiles of 512 threads reach
-// 26.5-28.4 GLUPS against 22.1-24 for 192 x 2), other float32 tiles two.
+// 25.2-28.4 GLUPS, 192 x 2 tiles 22.1 on 672), other float32 tiles two.
 // Four psi planes of (by + 2)(bx + 2) values must fit the 160 KB of LDS of a
 // CU.
 int default_block_x(int nx, long long cap, int threads, int min_rows) {
