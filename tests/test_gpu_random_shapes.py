@@ -58,3 +58,26 @@ def test_random_box_and_launch_shape(case):
     g["sim"].close()
     o = gc.run_oracle(rho0, 6, collision=coll, forcing=forcing, tau=0.9)
     assert float(np.abs(g["state"] - o["state"]).max()) < F64_TOL
+
+
+@pytest.mark.parametrize("case", range(0, 20, 2))
+def test_random_box_and_launch_shape_f32(case):
+    """The same boxes and launch shapes in FP32 shifted storage: density
+    within 2e-6 relative of the FP64 oracle after 6 steps (the FP32 storage
+    rounding floor over a few steps)."""
+    from paper_1905_09554_amd import lbsc
+    (nx, ny, nz), op, tuning = _cases()[case]
+    rng = np.random.default_rng(case)
+    rho0 = 1.0 + 0.4 * rng.random((nz, ny, nx))
+    coll = "mrt" if op == "mrt" else "bgk"
+    forcing = "shift" if op == "shift" else "guo"
+    try:
+        g = gc.run_gpu(rho0, 6, collision=coll, forcing=forcing, tau=0.9, tuning=tuning,
+                       precision="f32", want_state=False)
+    except lbsc.LbscError as e:
+        pytest.skip("launch shape rejected: %s" % e)
+    g["sim"].close()
+    o = gc.run_oracle(rho0, 6, collision=coll, forcing=forcing, tau=0.9)
+    rel = float((np.abs(g["rho"] - o["rho"]) / o["rho"]).max())
+    print("case %d f32: max rel drho %.2e" % (case, rel), flush=True)
+    assert rel < 2e-6
