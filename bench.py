@@ -266,6 +266,18 @@ def run_small_box(steps=1000, oracle=True):
     return out
 
 
+def cpu_model():
+    """The host CPU's model name, from /proc/cpuinfo where there is one."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(rho0, info, nz_sample=16, steps=40):
     """The float64 oracle on the host: the first nz_sample planes of the same
     input as a periodic slab, `steps` steps, reported in MLUPS."""
@@ -282,7 +294,7 @@ def cpu_baseline(rho0, info, nz_sample=16, steps=40):
         f = lbm.step(f, p)
     dt = time.perf_counter() - t0
     return {"value": round(sample.size * steps / dt / 1e6, 3), "unit": "MLUPS",
-            "cores": torch.get_num_threads(), "kind": "oracle",
+            "cores": torch.get_num_threads(), "kind": "oracle", "cpu_model": cpu_model(),
             "sample": "%dx%dx%d periodic slab (first %d planes of the benchmark input), "
                       "%s float64, %d steps, %.1f s" % (sample.shape[2], sample.shape[1],
                                                         nz_sample, nz_sample, info["collision"],
