@@ -133,6 +133,38 @@ def run_gpu(rho0, info, precision, steps, warmup):
     }
 
 
+def run_two_kernel(rho0, info, precision, reps=100):
+    """The same step in its two-kernel form (psi written to global memory,
+    then read back as a stencil by the colliding kernel): HIP-event time per
+    step on the library's stream, the unfused baseline beside the fused
+    kernel's kernel_ms."""
+    import torch
+    from paper_1905_09554_amd import lbsc
+
+    nz, ny, nx = rho0.shape
+    prm = lbsc.make_params(nx, ny, nz, collision=info["collision"], precision=precision,
+                           G=info["G"], tau=info["tau"], rho_ref=1.0)
+    sim = lbsc.Simulation(rho0, prm, device="cuda:0")
+    sim.set_tuning(two_kernel=1)
+    stream = sim.stream
+    sim.step(10)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        ev0.record(stream)
+        sim.step(reps)
+        ev1.record(stream)
+    ev1.synchronize()
+    per_step_s = ev0.elapsed_time(ev1) / 1e3 / reps
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return {"kernel_ms": round(per_step_s * 1e3, 4),
+            "mlups": round(rho0.size / per_step_s / 1e6, 1), "steps": reps,
+            "values_per_node": 59, "dtype": precision}
+
+
 def run_batch(steps, warmup):
     """The 64-ligament dispersion sweep (uneven boxes, 3.9e8 nodes) in one
     batch: MLUPS with one launch per step and with one persistent launch."""
@@ -311,6 +343,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched sweep figure")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost figure")
     ap.add_argument("--no-small", action="store_true", help="skip the 32x32x64 small-box figure")
+    ap.add_argument("--no-two-kernel", action="store_true",
+                    help="skip the unfused two-kernel baseline figure")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the step is single-GPU; see the design notes "
@@ -331,6 +365,12 @@ def main():
     if not args.no_fp64:
         f64 = run_gpu(rho0, info, "f64", max(50, args.steps // 2), args.warmup)
         print("f64 done: %.0f MLUPS" % f64["mlups"], file=sys.stderr, flush=True)
+    two = None
+    if not args.no_two_kernel:
+        two = run_two_kernel(rho0, info, "f32")
+        two["fused_kernel_ms"] = round(f32["kernel_ms"], 4)
+        two["fused_speedup"] = round(two["kernel_ms"] / f32["kernel_ms"], 3)
+        print("two-kernel done: %.3f ms per step" % two["kernel_ms"], file=sys.stderr, flush=True)
     batch = None
     if not args.no_batch:
         batch = run_batch(max(20, args.steps // 5), 5)
@@ -379,6 +419,8 @@ def main():
                         "kernel_ms": round(f64["kernel_ms"], 4), "roofline": f64["roofline"],
                         "mass_drift_per_1000": f64["mass_drift_per_1000"],
                         "tuning": f64["tuning"]}
+    if two:
+        line["two_kernel_baseline"] = two
     if batch:
         line["batched"] = batch
     if small:

@@ -101,6 +101,10 @@ typedef struct lbsc_tuning {
   int32_t persistent;  /* 1: all steps of one lbsc_step call in one cooperative
                           launch with grid barriers; 0: one launch per step   */
   int32_t block_x;     /* columns per tile; 0 = the default above             */
+  int32_t two_kernel;  /* 1: the two-kernel form of the step (psi written to
+                          global memory by one kernel, read as a stencil by
+                          the next), a baseline for the fused kernel; single
+                          box with one launch per step only; 0: fused       */
 } lbsc_tuning;
 
 /* Bytes of device memory a context with these parameters needs: two

@@ -74,6 +74,7 @@ struct lbsc_ctx {
   unsigned* dsync;               // grid-barrier words (count, generation, error, 2 tile counters)
   double* part;                  // diagnostic partial sums
   double* dout;                  // diagnostic results: 4 + max nz doubles
+  void* psi;                     // psi field of the two-kernel step (single box), or null
   int64_t step;
   AdjWork adj;
   std::string err;
@@ -233,6 +234,7 @@ lbsc_tuning default_tuning(const lbsc_params* p, int32_t n) {
   t.pop_pad = -1;
   t.nodes_per_thread = 1;
   t.persistent = 0;
+  t.two_kernel = 0;
   // float64 (about 200 VGPRs, 2 waves per SIMD): 256-thread groups, two per
   // CU, so one group's loads overlap the other's collision.  float32 (about
   // 110 VGPRs): 512-thread groups, two per CU; boxes with rows of at most 256
@@ -279,11 +281,12 @@ size_t lattice_bytes(const lbsc_params& p, long long pad) {
 // Sizes of the aux area (tile capacity: the finest tiling allowed, one row of
 // min(nx, kMinBlockX) columns per plane).
 struct AuxSizes {
-  size_t members, tiles, sync, part, out, total;
+  size_t members, tiles, sync, part, out, psi, total;
   long long tile_cap;
 };
 
-AuxSizes aux_sizes(int32_t n, const lbsc_params* p) {
+// with_psi: room for the psi field of the two-kernel step form (single box).
+AuxSizes aux_sizes(int32_t n, const lbsc_params* p, bool with_psi) {
   AuxSizes s;
   long long cap = 0;
   int max_blocks = 0, max_nz = 0;
@@ -302,14 +305,15 @@ AuxSizes aux_sizes(int32_t n, const lbsc_params* p) {
   s.sync = kAlign;
   s.part = align_up((size_t)max_blocks * 8 * sizeof(double));
   s.out = align_up((size_t)(4 + max_nz) * sizeof(double));
-  s.total = s.members + s.tiles + s.sync + s.part + s.out;
+  s.psi = with_psi ? align_up((size_t)nodes(p[0]) * elem_size(p[0])) : 0;
+  s.total = s.members + s.tiles + s.sync + s.part + s.out + s.psi;
   return s;
 }
 
-size_t batch_bytes(int32_t n, const lbsc_params* p, long long pad) {
+size_t batch_bytes(int32_t n, const lbsc_params* p, long long pad, bool with_psi) {
   size_t total = 0;
   for (int32_t i = 0; i < n; ++i) total += 2 * lattice_bytes(p[i], pad);
-  return total + aux_sizes(n, p).total;
+  return total + aux_sizes(n, p, with_psi).total;
 }
 
 int hip_fail(lbsc_ctx* c, hipError_t e, const char* what) {
@@ -362,7 +366,7 @@ int create(lbsc_ctx** out, int32_t n, const lbsc_params* p, const double* const*
   if (((uintptr_t)dev_buf) % kAlign != 0)
     return fail(&g_init_err, LBSC_EINVAL, "dev_buf must be 256-byte aligned");
   const long long pad = batch ? kDefaultPad : kMaxPad;
-  const size_t need = batch_bytes(n, p, pad);
+  const size_t need = batch_bytes(n, p, pad, !batch);
   if (dev_bytes < need)
     return fail(&g_init_err, LBSC_EINVAL,
                 "dev_bytes " + std::to_string(dev_bytes) + " < required " + std::to_string(need));
@@ -404,7 +408,7 @@ int create(lbsc_ctx** out, int32_t n, const lbsc_params* p, const double* const*
     mm.lat[1] = c->buf + off + mm.lat_bytes;
     off += 2 * mm.lat_bytes;
   }
-  const AuxSizes ax = aux_sizes(n, p);
+  const AuxSizes ax = aux_sizes(n, p, !batch);
   c->tile_cap = ax.tile_cap;
   c->dmembers = (lbsc::BatchMember*)(c->buf + off);
   off += ax.members;
@@ -415,6 +419,8 @@ int create(lbsc_ctx** out, int32_t n, const lbsc_params* p, const double* const*
   c->part = (double*)(c->buf + off);
   off += ax.part;
   c->dout = (double*)(c->buf + off);
+  off += ax.out;
+  c->psi = ax.psi ? (void*)(c->buf + off) : nullptr;
 
   // Stage each rho0 in the member's second lattice (19 N values >= N
   // doubles), then build the state in the first.
@@ -614,12 +620,12 @@ extern "C" {
 
 size_t lbsc_state_bytes(const lbsc_params* p) {
   if (check_params(p, nullptr) != LBSC_OK) return 0;
-  return batch_bytes(1, p, kMaxPad);
+  return batch_bytes(1, p, kMaxPad, true);
 }
 
 size_t lbsc_batch_state_bytes(int32_t n, const lbsc_params* p) {
   if (check_batch(n, p, nullptr) != LBSC_OK) return 0;
-  return batch_bytes(n, p, kDefaultPad);
+  return batch_bytes(n, p, kDefaultPad, false);
 }
 
 int lbsc_init_fields(lbsc_ctx** out, const lbsc_params* p, const double* rho0_host,
@@ -648,9 +654,14 @@ int lbsc_step(lbsc_ctx* c, int64_t nsteps) {
   if (c->batch || c->tune.persistent) return step_batch(c, nsteps);
   Member& m0 = c->m[0];
   for (int64_t i = 0; i < nsteps; ++i) {
-    hipError_t e = lbsc::launch_step(m0.p.precision, m0.p.collision, m0.p.forcing,
-                                     c->tune.threads, c->tune.nodes_per_thread, m0.lat[c->cur],
-                                     m0.lat[c->cur ^ 1], m0.a, c->stream);
+    hipError_t e =
+        c->tune.two_kernel
+            ? lbsc::launch_step_two_kernel(m0.p.precision, m0.p.collision, m0.p.forcing,
+                                           m0.lat[c->cur], c->psi, m0.lat[c->cur ^ 1], m0.a,
+                                           c->stream)
+            : lbsc::launch_step(m0.p.precision, m0.p.collision, m0.p.forcing, c->tune.threads,
+                                c->tune.nodes_per_thread, m0.lat[c->cur], m0.lat[c->cur ^ 1],
+                                m0.a, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "step launch");
     c->cur ^= 1;
     c->step += 1;
@@ -748,12 +759,17 @@ int lbsc_set_tuning(lbsc_ctx* c, const lbsc_tuning* t) {
     return fail(&c->err, LBSC_EINVAL, "a batch keeps the default population padding");
   if (t->persistent != 0 && t->persistent != 1)
     return fail(&c->err, LBSC_EINVAL, "persistent must be 0 or 1");
+  if (t->two_kernel != 0 && t->two_kernel != 1)
+    return fail(&c->err, LBSC_EINVAL, "two_kernel must be 0 or 1");
+  if (t->two_kernel && (c->batch || t->persistent))
+    return fail(&c->err, LBSC_EINVAL, "the two-kernel step form is for a single box, one launch per step");
   if (t->z_chunk) n.z_chunk = t->z_chunk;
   n.block_y = t->block_y;
   n.block_x = t->block_x;
   n.xcd_remap = t->xcd_remap ? 1 : 0;
   n.pop_pad = c->batch ? -1 : t->pop_pad;
   n.persistent = t->persistent;
+  n.two_kernel = t->two_kernel;
   for (Member& mm : c->m) {
     const lbsc::StepArgs na = make_args(mm.p, n, pad_of(n));
     if (na.ps != mm.a.ps) {

@@ -335,6 +335,38 @@ __device__ inline int remap_xcd(int b, int nb) {
   return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
+// psi at a node and its 18 neighbours: c; the axis neighbours x+ x- y+ y-
+// z+ z-; the diagonal pairs (+,+) (-,-) (+,-) (-,+) in the xy, xz and yz
+// planes.
+template <class R>
+struct Psi19 {
+  R c, xp, xm, yp, ym, zp, zm;
+  R xy_pp, xy_mm, xy_pm, xy_mp, xz_pp, xz_mm, xz_pm, xz_mp, yz_pp, yz_mm, yz_pm, yz_mp;
+};
+
+// Shan-Chen force F = -G psi(x) sum_a w_a psi(x + c_a) c_a (Eq. SC_force),
+// axis links weight 1/18, diagonals 1/36, summed as differences of opposite
+// neighbours.  Both step forms call this, so they agree bitwise.
+template <class R>
+__device__ inline void sc_force(const Psi19<R>& q, R G, R& Fx, R& Fy, R& Fz) {
+  const R ax = q.xp - q.xm;
+  const R ay = q.yp - q.ym;
+  const R az = q.zp - q.zm;
+  const R dxy = q.xy_pp - q.xy_mm;
+  const R dxmy = q.xy_pm - q.xy_mp;
+  const R dxz = q.xz_pp - q.xz_mm;
+  const R dxmz = q.xz_pm - q.xz_mp;
+  const R dyz = q.yz_pp - q.yz_mm;
+  const R dymz = q.yz_pm - q.yz_mp;
+  const R sx = ax * R(1.0 / 18.0) + (dxy + dxmy + dxz + dxmz) * R(1.0 / 36.0);
+  const R sy = ay * R(1.0 / 18.0) + (dxy - dxmy + dyz + dymz) * R(1.0 / 36.0);
+  const R sz = az * R(1.0 / 18.0) + (dxz - dxmz + dyz - dymz) * R(1.0 / 36.0);
+  const R gpsi = -G * q.c;
+  Fx = gpsi * sx;
+  Fy = gpsi * sy;
+  Fz = gpsi * sz;
+}
+
 // ---------------------------------------------------------------- the step
 // One work-group of NT threads owns the tile of columns [x0, x0 + bx) and
 // rows [y0, y0 + by) (bx * by <= K NT) over planes [z0, z1); each thread
@@ -449,20 +481,28 @@ __device__ inline void step_tile(const T* __restrict__ src, T* __restrict__ dst,
       const int x = lx[k] + 1;  // LDS column; x - 1 and x + 1 are in the ring
       const int xm = x - 1, xp = x + 1;
       const int rm = ly[k] * lw, rc = (ly[k] + 1) * lw, rp = (ly[k] + 2) * lw;
-      // sum_a w_a psi(x + c_a) c_a, axis links weight 1/18, diagonals 1/36.
-      const R ax = pc[rc + xp] - pc[rc + xm];
-      const R ay = pc[rp + x] - pc[rm + x];
-      const R az = pp[rc + x] - pm[rc + x];
-      const R dxy = pc[rp + xp] - pc[rm + xm];   // (+,+) minus (-,-)
-      const R dxmy = pc[rm + xp] - pc[rp + xm];  // (+,-) minus (-,+)
-      const R dxz = pp[rc + xp] - pm[rc + xm];
-      const R dxmz = pm[rc + xp] - pp[rc + xm];
-      const R dyz = pp[rp + x] - pm[rm + x];
-      const R dymz = pm[rp + x] - pp[rm + x];
-      const R sx = ax * R(1.0 / 18.0) + (dxy + dxmy + dxz + dxmz) * R(1.0 / 36.0);
-      const R sy = ay * R(1.0 / 18.0) + (dxy - dxmy + dyz + dymz) * R(1.0 / 36.0);
-      const R sz = az * R(1.0 / 18.0) + (dxz - dxmz + dyz - dymz) * R(1.0 / 36.0);
-      const R gpsi = -ph.G * pc[rc + x];
+      Psi19<R> q;
+      q.c = pc[rc + x];
+      q.xp = pc[rc + xp];
+      q.xm = pc[rc + xm];
+      q.yp = pc[rp + x];
+      q.ym = pc[rm + x];
+      q.zp = pp[rc + x];
+      q.zm = pm[rc + x];
+      q.xy_pp = pc[rp + xp];
+      q.xy_mm = pc[rm + xm];
+      q.xy_pm = pc[rm + xp];
+      q.xy_mp = pc[rp + xm];
+      q.xz_pp = pp[rc + xp];
+      q.xz_mm = pm[rc + xm];
+      q.xz_pm = pm[rc + xp];
+      q.xz_mp = pp[rc + xm];
+      q.yz_pp = pp[rp + x];
+      q.yz_mm = pm[rm + x];
+      q.yz_pm = pm[rp + x];
+      q.yz_mp = pp[rm + x];
+      R Fx, Fy, Fz;
+      sc_force<R>(q, ph.G, Fx, Fy, Fz);
       const unsigned idx =
           (unsigned)z * (unsigned)plane + (unsigned)((y0 + ly[k]) * nx + x0 + lx[k]);
       if (a.rho_out) {
@@ -473,7 +513,7 @@ __device__ inline void step_tile(const T* __restrict__ src, T* __restrict__ dst,
         for (int q = 0; q < Q; ++q) s += cur[k][q];
         static_cast<T*>(a.rho_out)[idx] = T(ph.rho_ref + s);
       }
-      collide<R, COLL, FORC>(cur[k], gpsi * sx, gpsi * sy, gpsi * sz, ph);
+      collide<R, COLL, FORC>(cur[k], Fx, Fy, Fz, ph);
       // Written once and read only in the next step: non-temporal stores keep
       // them from evicting the rows the neighbouring tiles still re-read.
 #pragma unroll
@@ -498,6 +538,71 @@ k_step(const T* __restrict__ src, T* __restrict__ dst, StepArgs a) {
   const int ntxy = a.ntiles_x * a.ntiles_y;
   step_tile<T, COLL, FORC, NT, K>(src, dst, a, b % ntxy, b / ntxy,
                                   reinterpret_cast<T*>(smem_raw));
+}
+
+// Two-kernel form of the step, the baseline the fused kernel is measured
+// against: K1 pulls the populations of every node and writes psi to global
+// memory; K2 pulls them again, reads the psi stencil from global memory and
+// collides.  That moves 19 + 1 + 19 + 1 + 19 = 59 values per node (with
+// perfect reuse of the psi stencil) instead of 38.  Same arithmetic as the
+// fused kernel, so the results agree bitwise.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_density_psi(const T* __restrict__ src, T* __restrict__ psi, StepArgs a) {
+  using R = T;
+  const Phys<R> ph = make_phys<R>(a);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / a.plane);
+    const Nbr nb = neighbours(x, y, z, a.nx, a.ny, a.nz, a.plane);
+    R f[Q];
+    pull<T, R>(src, a.ps, nb, f);
+    R s = R(0);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s += f[q];
+    psi[i] = T(psi_of(ph.rho_ref + s, ph.psi_rho0, ph.inv_psi_rho0));
+  }
+}
+
+template <class T, int COLL, int FORC>
+__global__ void __launch_bounds__(256)
+k_step_psi(const T* __restrict__ src, const T* __restrict__ psi, T* __restrict__ dst,
+           StepArgs a) {
+  using R = T;
+  const Phys<R> ph = make_phys<R>(a);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / a.plane);
+    const Nbr b = neighbours(x, y, z, a.nx, a.ny, a.nz, a.plane);
+    R f[Q];
+    pull<T, R>(src, a.ps, b, f);
+    Psi19<R> q;
+    q.c = R(psi[b.zo[1] + b.yo[1] + b.xo[1]]);
+    q.xp = R(psi[b.zo[1] + b.yo[1] + b.xo[2]]);
+    q.xm = R(psi[b.zo[1] + b.yo[1] + b.xo[0]]);
+    q.yp = R(psi[b.zo[1] + b.yo[2] + b.xo[1]]);
+    q.ym = R(psi[b.zo[1] + b.yo[0] + b.xo[1]]);
+    q.zp = R(psi[b.zo[2] + b.yo[1] + b.xo[1]]);
+    q.zm = R(psi[b.zo[0] + b.yo[1] + b.xo[1]]);
+    q.xy_pp = R(psi[b.zo[1] + b.yo[2] + b.xo[2]]);
+    q.xy_mm = R(psi[b.zo[1] + b.yo[0] + b.xo[0]]);
+    q.xy_pm = R(psi[b.zo[1] + b.yo[0] + b.xo[2]]);
+    q.xy_mp = R(psi[b.zo[1] + b.yo[2] + b.xo[0]]);
+    q.xz_pp = R(psi[b.zo[2] + b.yo[1] + b.xo[2]]);
+    q.xz_mm = R(psi[b.zo[0] + b.yo[1] + b.xo[0]]);
+    q.xz_pm = R(psi[b.zo[0] + b.yo[1] + b.xo[2]]);
+    q.xz_mp = R(psi[b.zo[2] + b.yo[1] + b.xo[0]]);
+    q.yz_pp = R(psi[b.zo[2] + b.yo[2] + b.xo[1]]);
+    q.yz_mm = R(psi[b.zo[0] + b.yo[0] + b.xo[1]]);
+    q.yz_pm = R(psi[b.zo[0] + b.yo[2] + b.xo[1]]);
+    q.yz_mp = R(psi[b.zo[2] + b.yo[0] + b.xo[1]]);
+    R Fx, Fy, Fz;
+    sc_force<R>(q, ph.G, Fx, Fy, Fz);
+    collide<R, COLL, FORC>(f, Fx, Fy, Fz, ph);
+#pragma unroll
+    for (int qq = 0; qq < Q; ++qq)
+      __builtin_nontemporal_store(T(f[qq]), &dst[(long long)qq * a.ps + i]);
+  }
 }
 
 // Batch of boxes (uneven sizes and parameters), one step: the tile table
@@ -1236,6 +1341,30 @@ static hipError_t step_t(int threads, int npt, const void* src, void* dst, const
     default: step_nt<T, COLL, FORC, 1024>(npt, grid, lds, in, out, a, s); break;
   }
   return hipGetLastError();
+}
+
+template <class T, int COLL, int FORC>
+static hipError_t step_two_t(const void* src, void* psi, void* dst, const StepArgs& a,
+                             hipStream_t s) {
+  const int g = grid_for(a.n, 256);
+  hipLaunchKernelGGL(k_density_psi<T>, dim3(g), dim3(256), 0, s, (const T*)src, (T*)psi, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_step_psi<T, COLL, FORC>), dim3(g), dim3(256), 0, s, (const T*)src,
+                     (const T*)psi, (T*)dst, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_two_kernel(int prec, int coll, int forc, const void* src, void* psi,
+                                  void* dst, const StepArgs& a, hipStream_t s) {
+  if (prec == 0) {
+    if (coll == kMRT) return step_two_t<double, kMRT, kGuo>(src, psi, dst, a, s);
+    if (forc == kShift) return step_two_t<double, kBGK, kShift>(src, psi, dst, a, s);
+    return step_two_t<double, kBGK, kGuo>(src, psi, dst, a, s);
+  }
+  if (coll == kMRT) return step_two_t<float, kMRT, kGuo>(src, psi, dst, a, s);
+  if (forc == kShift) return step_two_t<float, kBGK, kShift>(src, psi, dst, a, s);
+  return step_two_t<float, kBGK, kGuo>(src, psi, dst, a, s);
 }
 
 hipError_t launch_step(int prec, int coll, int forc, int threads, int npt, const void* src,

@@ -74,6 +74,10 @@ hipError_t launch_init(int prec, void* lat, const double* rho0_dev, const StepAr
                        hipStream_t s);
 hipError_t launch_step(int prec, int coll, int forc, int threads, int npt, const void* src,
                        void* dst, const StepArgs& a, hipStream_t s);
+// The two-kernel form of one step (psi to global memory, then the step from
+// the psi stencil); psi holds n values of the storage type.
+hipError_t launch_step_two_kernel(int prec, int coll, int forc, const void* src, void* psi,
+                                  void* dst, const StepArgs& a, hipStream_t s);
 hipError_t launch_batch(const BatchLaunch& L, hipStream_t s);
 // psi_scratch: n doubles of device scratch (the idle lattice) for psi(rho).
 hipError_t launch_moments(int prec, const void* lat, double* rho, double* u, double* p,

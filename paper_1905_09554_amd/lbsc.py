@@ -50,7 +50,8 @@ class Tuning(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("z_chunk", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("block_y", ctypes.c_int32),
                 ("pop_pad", ctypes.c_int32), ("nodes_per_thread", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("block_x", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("block_x", ctypes.c_int32),
+                ("two_kernel", ctypes.c_int32)]
 
 
 class LbscError(RuntimeError):
@@ -278,9 +279,9 @@ class Simulation:
 
     # -- launch shape
     def set_tuning(self, threads=0, z_chunk=0, xcd_remap=1, block_y=0, pop_pad=-1,
-                   nodes_per_thread=0, persistent=0, block_x=0):
+                   nodes_per_thread=0, persistent=0, block_x=0, two_kernel=0):
         t = Tuning(threads, z_chunk, xcd_remap, block_y, pop_pad, nodes_per_thread, persistent,
-                   block_x)
+                   block_x, two_kernel)
         _check(library().lbsc_set_tuning(self._ctx, ctypes.byref(t)), self._ctx)
 
     def get_tuning(self):
@@ -289,7 +290,7 @@ class Simulation:
         return {"threads": t.threads, "z_chunk": t.z_chunk, "xcd_remap": t.xcd_remap,
                 "block_y": t.block_y, "pop_pad": t.pop_pad,
                 "nodes_per_thread": t.nodes_per_thread, "persistent": t.persistent,
-                "block_x": t.block_x}
+                "block_x": t.block_x, "two_kernel": t.two_kernel}
 
 
 class Batch:

@@ -141,6 +141,24 @@ def test_launch_shape_does_not_change_results_bitwise(precision, box, shapes):
             assert np.array_equal(ref, g["state"]), t
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("coll,forcing", [("bgk", "guo"), ("mrt", "guo"), ("bgk", "shift")])
+def test_two_kernel_form_matches_the_fused_step_bitwise(precision, coll, forcing):
+    """The two-kernel form (psi through global memory) does the fused
+    kernel's arithmetic in the same order: identical populations."""
+    rho0 = gc.ligament(40, 36, 30, 8.0, 0.1, 1, noise=1e-4)
+    fused = gc.run_gpu(rho0, 9, collision=coll, forcing=forcing, precision=precision)
+    fused["sim"].close()
+    two = gc.run_gpu(rho0, 9, collision=coll, forcing=forcing, precision=precision,
+                     tuning=dict(two_kernel=1))
+    assert two["sim"].get_tuning()["two_kernel"] == 1
+    two["sim"].close()
+    assert np.array_equal(fused["state"], two["state"])
+    if precision == "f64":
+        o = gc.run_oracle(rho0, 9, collision=coll, forcing=forcing)
+        assert float(np.abs(two["state"] - o["state"]).max()) < 1e-12
+
+
 def test_zero_steps_is_the_initial_state():
     rho0 = _c1()
     g = gc.run_gpu(rho0, 0)
