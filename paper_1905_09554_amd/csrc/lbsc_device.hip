@@ -396,7 +396,7 @@ __device__ inline void step_tile(const T* __restrict__ src, T* __restrict__ dst,
   const int z1 = min(nz, z0 + a.zchunk);
 
   const int tid = threadIdx.x;
-  int lx[K], ly[K];
+  int lx[K], ly[K], cx[K], cy[K];
   bool interior[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -404,6 +404,8 @@ __device__ inline void step_tile(const T* __restrict__ src, T* __restrict__ dst,
     lx[k] = i % a.bx;
     ly[k] = i / a.bx;
     interior[k] = ly[k] < bye && lx[k] < bxe;
+    cx[k] = min(lx[k], bxe - 1);  // the node a thread past the edge stands in for
+    cy[k] = min(ly[k], bye - 1);
   }
   // Halo ring: rows -1 and bye over columns -1..bxe, then columns -1 and bxe
   // over rows 0..bye-1.  A tile of whole rows has no halo columns of its own:
@@ -415,53 +417,69 @@ __device__ inline void step_tile(const T* __restrict__ src, T* __restrict__ dst,
 
   R cur[K][Q], nxt[K][Q];
 
+  // psi of halo node h of plane z into its LDS row.
+  auto halo_node = [&](int h, int z, R* lp) {
+    int hl, hc;
+    if (whole_rows) {
+      hl = h < bxe ? -1 : bye;
+      hc = h < bxe ? h : h - bxe;
+    } else if (h < 2 * hrow) {
+      hl = h < hrow ? -1 : bye;
+      hc = (h < hrow ? h : h - hrow) - 1;
+    } else {
+      const int g = h - 2 * hrow;
+      hc = g < bye ? -1 : bxe;
+      hl = g < bye ? g : g - bye;
+    }
+    int hy = y0 + hl, hx = x0 + hc;
+    hy = hy < 0 ? hy + ny : (hy >= ny ? hy - ny : hy);
+    hx = hx < 0 ? hx + nx : (hx >= nx ? hx - nx : hx);
+    const Nbr nb = neighbours(hx, hy, z, nx, ny, nz, plane);
+    // All 19 loads are issued before the first add: left to itself, the
+    // scheduler pairs each load with its add to save registers, which puts
+    // 19 memory latencies in a row.
+    R f[Q];
+    pull<T, R>(src, ps, nb, f);
+    __builtin_amdgcn_sched_barrier(0);
+    R s = R(0);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s += f[q];
+    const R v = psi_of(ph.rho_ref + s, ph.psi_rho0, ph.inv_psi_rho0);
+    R* row = lp + (hl + 1) * lw;
+    row[hc + 1] = v;
+    if (whole_rows && hc == 0) row[bxe + 1] = v;
+    if (whole_rows && hc == bxe - 1) row[0] = v;
+  };
+
   // Pulls plane z: psi of the tile plus its halo ring into LDS slot `slot`;
-  // interior populations into `keep`.
+  // interior populations into `keep`.  Threads past the tile's ragged edge
+  // pull the clamped in-tile node (cx, cy) and store its psi a second time,
+  // the same value to the same LDS word as its owner.  Loads and their uses
+  // under a branch would leave the compiler unsure whether they have landed
+  // at the end of the plane loop, and it would wait there for every
+  // outstanding store before the next plane's loads.  The first round of the
+  // halo ring is issued before the interior sums wait, so that both sets of
+  // loads are in flight together.
   auto load_plane = [&](int z, int slot, R(&keep)[K][Q]) {
     R* lp = lds + slot * lplane;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      if (interior[k]) {
-        const Nbr nb = neighbours(x0 + lx[k], y0 + ly[k], z, nx, ny, nz, plane);
-        pull<T, R>(src, ps, nb, keep[k]);
-      }
+      const Nbr nb = neighbours(x0 + cx[k], y0 + cy[k], z, nx, ny, nz, plane);
+      pull<T, R>(src, ps, nb, keep[k]);
     }
+    if (tid < nhalo) halo_node(tid, z, lp);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      if (interior[k]) {
-        R s = R(0);
+      R s = R(0);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) s += keep[k][q];
-        const R v = psi_of(ph.rho_ref + s, ph.psi_rho0, ph.inv_psi_rho0);
-        R* row = lp + (ly[k] + 1) * lw;
-        row[lx[k] + 1] = v;
-        if (whole_rows && lx[k] == 0) row[bxe + 1] = v;
-        if (whole_rows && lx[k] == bxe - 1) row[0] = v;
-      }
+      for (int q = 0; q < Q; ++q) s += keep[k][q];
+      const R v = psi_of(ph.rho_ref + s, ph.psi_rho0, ph.inv_psi_rho0);
+      R* row = lp + (cy[k] + 1) * lw;
+      row[cx[k] + 1] = v;
+      if (whole_rows && cx[k] == 0) row[bxe + 1] = v;
+      if (whole_rows && cx[k] == bxe - 1) row[0] = v;
     }
-    for (int h = tid; h < nhalo; h += NT) {
-      int hl, hc;
-      if (whole_rows) {
-        hl = h < bxe ? -1 : bye;
-        hc = h < bxe ? h : h - bxe;
-      } else if (h < 2 * hrow) {
-        hl = h < hrow ? -1 : bye;
-        hc = (h < hrow ? h : h - hrow) - 1;
-      } else {
-        const int g = h - 2 * hrow;
-        hc = g < bye ? -1 : bxe;
-        hl = g < bye ? g : g - bye;
-      }
-      int hy = y0 + hl, hx = x0 + hc;
-      hy = hy < 0 ? hy + ny : (hy >= ny ? hy - ny : hy);
-      hx = hx < 0 ? hx + nx : (hx >= nx ? hx - nx : hx);
-      const Nbr nb = neighbours(hx, hy, z, nx, ny, nz, plane);
-      const R v = psi_of(ph.rho_ref + pull_sum<T, R>(src, ps, nb), ph.psi_rho0, ph.inv_psi_rho0);
-      R* row = lp + (hl + 1) * lw;
-      row[hc + 1] = v;
-      if (whole_rows && hc == 0) row[bxe + 1] = v;
-      if (whole_rows && hc == bxe - 1) row[0] = v;
-    }
+    for (int h = tid + NT; h < nhalo; h += NT) halo_node(h, z, lp);
   };
 
   const int zprev = z0 == 0 ? nz - 1 : z0 - 1;
