@@ -49,8 +49,8 @@ struct AdjWork {
   char* rho = nullptr;   // segment densities
   char* P[2] = {nullptr, nullptr};
   char* R[2] = {nullptr, nullptr};
-  char* fbar = nullptr;  // 3 n values
-  char* psi = nullptr;   // n values
+  char* psi_fbar = nullptr;    // 3 n values: psi(x) dL/dF(x)
+  char* fbar_dot_v = nullptr;  // n values: dL/dF(x) . sum_b w_b psi(x + c_b) c_b
   double* partial = nullptr;
   double* acc = nullptr;  // dL/dG, dL/dtau, dL/ds_bulk, dL/ds_ghost
   double rates[2] = {0.0, 0.0};  // dL/ds_bulk, dL/ds_ghost of the last backward pass
@@ -578,7 +578,7 @@ int set_state_of(lbsc_ctx* c, Member* mm, const void* host, size_t bytes) {
 // Workspace layout of the adjoint for a single box (lattices sized for the
 // largest padding so any tuning of the box fits).
 struct AdjLayout {
-  size_t lat, rho, cp, ring, rhos, P, R, fbar, psi, partial, acc, total;
+  size_t lat, rho, cp, ring, rhos, P, R, psi_fbar, fbar_dot_v, partial, acc, total;
   int ncp;
 };
 
@@ -594,11 +594,11 @@ AdjLayout adj_layout(const lbsc_params& p, int64_t nsteps, int32_t segment) {
   L.rhos = (size_t)segment * L.rho;
   L.P = 2 * L.lat;
   L.R = 2 * L.rho;
-  L.fbar = align_up(3 * (size_t)a.n * elem_size(p));
-  L.psi = align_up((size_t)a.n * elem_size(p));
+  L.psi_fbar = align_up(3 * (size_t)a.n * elem_size(p));
+  L.fbar_dot_v = align_up((size_t)a.n * elem_size(p));
   L.partial = align_up(4 * sizeof(double) * (size_t)lbsc::adj_blocks(a));
   L.acc = kAlign;
-  L.total = L.cp + L.ring + L.rhos + L.P + L.R + L.fbar + L.psi + L.partial + L.acc;
+  L.total = L.cp + L.ring + L.rhos + L.P + L.R + L.psi_fbar + L.fbar_dot_v + L.partial + L.acc;
   return L;
 }
 
@@ -842,10 +842,10 @@ int lbsc_adjoint_forward(lbsc_ctx* c, int64_t nsteps, int32_t segment, void* wor
   w.R[0] = base;
   w.R[1] = base + L.rho;
   base += L.R;
-  w.fbar = base;
-  base += L.fbar;
-  w.psi = base;
-  base += L.psi;
+  w.psi_fbar = base;
+  base += L.psi_fbar;
+  w.fbar_dot_v = base;
+  base += L.fbar_dot_v;
   w.partial = (double*)base;
   base += L.partial;
   w.acc = (double*)base;
@@ -892,8 +892,8 @@ int lbsc_adjoint_backward(lbsc_ctx* c, const double* rhobar_dev, double* rho0bar
   const int prec = mm.p.precision;
   lbsc::AdjArgs g;
   g.a = mm.a;
-  g.fbar = w.fbar;
-  g.psi = w.psi;
+  g.psi_fbar = w.psi_fbar;
+  g.fbar_dot_v = w.fbar_dot_v;
   g.partial = w.partial;
   w.have_rates = false;
   HIP_OR_FAIL(c, hipMemsetAsync(w.acc, 0, 4 * sizeof(double), c->stream));

@@ -998,7 +998,7 @@ __global__ void __launch_bounds__(256) k_adj_collide(AdjArgs g) {
   const T* __restrict__ pn = (const T*)g.p_next;
   const T* __restrict__ rn = (const T*)g.r_next;
   T* __restrict__ po = (T*)g.p_out;
-  T* __restrict__ fb = (T*)g.fbar;
+  T* __restrict__ pfb = (T*)g.psi_fbar;
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   double dG = 0.0, dtau = 0.0, dbulk = 0.0, dghost = 0.0;
   if (i < a.n) {
@@ -1023,7 +1023,6 @@ __global__ void __launch_bounds__(256) k_adj_collide(AdjArgs g) {
       if constexpr (CZ[b] != 0) vz += R(CZ[b]) * wp;
     });
     const R psi_c = psi_of(R(rho[i]), ph.psi_rho0, ph.inv_psi_rho0);
-    static_cast<T*>(g.psi)[i] = T(psi_c);  // for the transposed stencil of kernel B
     const R gpsi = -ph.G * psi_c;
     const R Fx = gpsi * vx, Fy = gpsi * vy, Fz = gpsi * vz;
     // Forward moments (as in the collision).
@@ -1206,9 +1205,12 @@ __global__ void __launch_bounds__(256) k_adj_collide(AdjArgs g) {
       if constexpr (CZ[q] != 0) v += R(CZ[q]) * jbz;
       po[(long long)q * a.ps + i] = T(v);
     });
-    fb[i] = T(Fbx);
-    fb[a.n + i] = T(Fby);
-    fb[2 * a.n + i] = T(Fbz);
+    // For kernel B: the local half of dL/dpsi(x) and the field its
+    // transposed stencil gathers.
+    static_cast<T*>(g.fbar_dot_v)[i] = T(Fbx * vx + Fby * vy + Fbz * vz);
+    pfb[i] = T(psi_c * Fbx);
+    pfb[a.n + i] = T(psi_c * Fby);
+    pfb[2 * a.n + i] = T(psi_c * Fbz);
     // dL/dG: F is linear in G.
     if (a.G != 0.0)
       dG = (double(Fbx) * double(Fx) + double(Fby) * double(Fy) + double(Fbz) * double(Fz)) / a.G;
@@ -1227,39 +1229,35 @@ __global__ void __launch_bounds__(256) k_adj_collide(AdjArgs g) {
 
 // r(x) = psi'(rho(x)) * dL/dpsi(x), with
 // dL/dpsi(x) = -G [ Fb(x) . sum_b w_b psi(x + c_b) c_b
-//                   + sum_b w_b psi(x - c_b) Fb(x - c_b) . c_b ].
+//                   + sum_b w_b c_b . (psi Fb)(x - c_b) ].
+// Kernel A stored the first term's dot product and the field psi Fb.
 template <class T>
 __global__ void __launch_bounds__(256) k_adj_psi(AdjArgs g) {
   using R = T;
   const StepArgs& a = g.a;
   const Phys<R> ph = make_phys<R>(a);
   const T* __restrict__ rho = (const T*)g.rho;
-  const T* __restrict__ psi = (const T*)g.psi;
-  const T* __restrict__ fb = (const T*)g.fbar;
+  const T* __restrict__ t1v = (const T*)g.fbar_dot_v;
+  const T* __restrict__ pfb = (const T*)g.psi_fbar;
   T* __restrict__ ro = (T*)g.r_out;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.n;
        i += (long long)gridDim.x * blockDim.x) {
     const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / a.plane);
     const Nbr nb = neighbours(x, y, z, a.nx, a.ny, a.nz, a.plane);
-    R t1 = R(0), t2 = R(0);
-    const R fx = R(fb[i]), fy = R(fb[a.n + i]), fz = R(fb[2 * a.n + i]);
+    R t2 = R(0);
     static_for<Q - 1>([&](auto bc) {
       constexpr int b = decltype(bc)::value + 1;
-      const unsigned ip = nb.zo[1 + CZ[b]] + nb.yo[1 + CY[b]] + nb.xo[1 + CX[b]];
       const unsigned im = nb.zo[1 - CZ[b]] + nb.yo[1 - CY[b]] + nb.xo[1 - CX[b]];
-      const R wpp = weight<R>(b) * R(psi[ip]);
-      const R wpm = weight<R>(b) * R(psi[im]);
-      R cf = R(0), cfm = R(0);
-      if constexpr (CX[b] != 0) { cf += R(CX[b]) * fx; cfm += R(CX[b]) * R(fb[im]); }
-      if constexpr (CY[b] != 0) { cf += R(CY[b]) * fy; cfm += R(CY[b]) * R(fb[a.n + im]); }
-      if constexpr (CZ[b] != 0) { cf += R(CZ[b]) * fz; cfm += R(CZ[b]) * R(fb[2 * a.n + im]); }
-      t1 += wpp * cf;
-      t2 += wpm * cfm;
+      R ch = R(0);
+      if constexpr (CX[b] != 0) ch += R(CX[b]) * R(pfb[im]);
+      if constexpr (CY[b] != 0) ch += R(CY[b]) * R(pfb[a.n + im]);
+      if constexpr (CZ[b] != 0) ch += R(CZ[b]) * R(pfb[2 * a.n + im]);
+      t2 += weight<R>(b) * ch;
     });
     const R r = R(rho[i]);
     const R dpsi = (sizeof(R) == 8) ? R(exp(-double(r) * double(ph.inv_psi_rho0)))
                                     : R(expf(-float(r) * float(ph.inv_psi_rho0)));
-    ro[i] = T(-ph.G * (t1 + t2) * dpsi);
+    ro[i] = T(-ph.G * (R(t1v[i]) + t2) * dpsi);
   }
 }
 

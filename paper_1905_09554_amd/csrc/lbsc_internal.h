@@ -61,8 +61,9 @@ struct AdjArgs {
   const void* r_next;
   void* p_out;
   void* r_out;
-  void* fbar;
-  void* psi;        // psi(rho_n) of every node (n values), written by kernel A for kernel B
+  // Written by kernel A for kernel B, per node x (Fb = dL/dF(x)):
+  void* psi_fbar;    // psi(x) Fb(x), three arrays of n values (x, y, z)
+  void* fbar_dot_v;  // Fb(x) . sum_b w_b psi(x + c_b) c_b, n values
   double* partial;  // accumulated over the whole backward pass, reduced once
 };
 
