@@ -409,6 +409,11 @@ def main():
         "copy_ceiling": {"gbs": COPY_CEILING_GBS,
                          "frac": round(f32["roofline"]["achieved"] / COPY_CEILING_GBS, 4)},
         "kernel_ms": round(f32["kernel_ms"], 4),
+        # Step kernel alone (HIP events, no diagnostics), and the measured HBM
+        # bytes per node-step from the counter runs.
+        "value_kernel_only": round(rho0.size / (f32["kernel_ms"] * 1e-3) / 1e6, 1),
+        "traffic_bytes_per_node": (round(f32["roofline"]["traffic"] / rho0.size, 2)
+                                   if f32["roofline"]["traffic"] else None),
         "hbm_frac_alg": round(f32["mlups"] * 1e6 * BYTES_PER_NODE["f32"] / 1e9 / HBM_PEAK_GBS, 4),
         "cpu_baseline": cpu,
         "mass_drift_per_1000": f32["mass_drift_per_1000"],
@@ -417,6 +422,7 @@ def main():
         line["fp64"] = {"value": round(f64["mlups"], 1), "unit": "MLUPS", "dtype": "f64",
                         "ms_per_step": round(f64["ms_per_step"], 4),
                         "kernel_ms": round(f64["kernel_ms"], 4), "roofline": f64["roofline"],
+                        "value_kernel_only": round(rho0.size / (f64["kernel_ms"] * 1e-3) / 1e6, 1),
                         "mass_drift_per_1000": f64["mass_drift_per_1000"],
                         "tuning": f64["tuning"]}
     if two:
