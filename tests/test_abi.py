@@ -117,3 +117,37 @@ def test_simulation_requires_built_library_and_raises_without_gpu():
         pytest.skip("host-only check")
     with pytest.raises(Exception):
         lbsc.Simulation(np.ones((4, 4, 4)), _params(nx=4, ny=4, nz=4), device="cuda:0")
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """sizeof and every field offset of lbsc_params, lbsc_diag and
+    lbsc_tuning as a C compiler lays them out from the header, against the
+    ctypes structures of the binding."""
+    structs = {"lbsc_params": lbsc.Params, "lbsc_diag": lbsc.Diag, "lbsc_tuning": lbsc.Tuning}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "lbsc.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('  printf("%s sizeof %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    seen = {}
+    for line in out.split("\n"):
+        if line:
+            cname, key, value = line.split()
+            seen[(cname, key)] = int(value)
+    for cname, py in structs.items():
+        assert seen[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert seen[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+    # every field the header declares is in the binding
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct lbsc_tuning \{(.*?)\} lbsc_tuning;", text, flags=re.S).group(1)
+    declared = re.findall(r"\b(\w+)\s*;", body)
+    assert declared == [f for f, _ in lbsc.Tuning._fields_]

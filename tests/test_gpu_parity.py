@@ -159,6 +159,24 @@ def test_two_kernel_form_matches_the_fused_step_bitwise(precision, coll, forcing
         assert float(np.abs(two["state"] - o["state"]).max()) < 1e-12
 
 
+def test_two_kernel_form_is_refused_where_it_does_not_apply():
+    """Single box, one launch per step only: a batch, the persistent launch
+    and values other than 0/1 are rejected, and the context keeps its
+    previous (fused) tuning."""
+    from paper_1905_09554_amd import lbsc
+    rho0 = gc.ligament(40, 36, 30, 8.0, 0.1, 1)
+    sim = lbsc.Simulation(rho0, lbsc.make_params(40, 36, 30))
+    for bad in (dict(two_kernel=1, persistent=1), dict(two_kernel=2)):
+        with pytest.raises(lbsc.LbscError):
+            sim.set_tuning(**bad)
+        assert sim.get_tuning()["two_kernel"] == 0
+    sim.close()
+    b = lbsc.Batch([rho0, rho0], [lbsc.make_params(40, 36, 30)] * 2)
+    with pytest.raises(lbsc.LbscError):
+        b.set_tuning(two_kernel=1)
+    b.close()
+
+
 def test_zero_steps_is_the_initial_state():
     rho0 = _c1()
     g = gc.run_gpu(rho0, 0)
