@@ -127,6 +127,29 @@ def lattice():
     return c, w
 
 
+def _inputs_ready(device, stream):
+    """The library's stream waits for torch's current stream, where device
+    inputs (such as dL/drho) were made."""
+    import torch
+    cur = torch.cuda.current_stream(device)
+    if cur != stream:
+        stream.wait_stream(cur)
+
+
+def _outputs_ready(device, stream, *tensors):
+    """Torch's current stream waits for the library's stream, which wrote the
+    device outputs; each output is also marked as used by that stream, so
+    that torch's caching allocator does not hand its memory to other work
+    before the stream is done with it."""
+    import torch
+    cur = torch.cuda.current_stream(device)
+    if cur != stream:
+        cur.wait_stream(stream)
+        for t in tensors:
+            if t is not None:
+                t.record_stream(stream)
+
+
 def _check(rc, ctx=None):
     if rc != LBSC_OK:
         msg = library().lbsc_last_error(ctx)
@@ -138,7 +161,10 @@ class Simulation:
 
     rho0: float64 array [nz, ny, nx] (host).  The device buffer is a torch
     uint8 tensor on ``device``; work goes to torch's current stream of that
-    device unless ``stream`` (a torch.cuda.Stream) is given.
+    device unless ``stream`` (a torch.cuda.Stream) is given.  With a stream
+    of its own, device tensors returned by a call are ordered after the
+    library's work on torch's current stream, and device inputs made on
+    torch's current stream before the call.
     """
 
     def __init__(self, rho0, params, device="cuda:0", stream=None):
@@ -206,6 +232,7 @@ class Simulation:
             self._ctx, ctypes.c_void_p(rho.data_ptr()),
             ctypes.c_void_p(u.data_ptr() if u is not None else 0),
             ctypes.c_void_p(pr.data_ptr() if pr is not None else 0)), self._ctx)
+        _outputs_ready(self.device, self.stream, rho, u, pr)
         return rho, u, pr
 
     def diagnostics(self, rho_v, rho_l):
@@ -242,6 +269,9 @@ class Simulation:
                                                         int(segment))
         if nbytes == 0:
             raise LbscError(LBSC_EINVAL, "invalid adjoint request")
+        if getattr(self, "_ws", None) is not None:
+            self.stream.synchronize()  # the old workspace may still be in use
+            self._ws = None
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self._ws.data_ptr()) % 256
         _check(library().lbsc_adjoint_forward(self._ctx, int(nsteps), int(segment),
@@ -257,6 +287,7 @@ class Simulation:
         _check(library().lbsc_rmin_gradient(self._ctx, float(rho_v), float(rho_l),
                                             ctypes.c_void_p(g.data_ptr()), ctypes.byref(r)),
                self._ctx)
+        _outputs_ready(self.device, self.stream, g)
         return g, r.value
 
     def adjoint_backward(self, rhobar):
@@ -264,10 +295,12 @@ class Simulation:
         import torch
         rhobar = rhobar.to(device=self.device, dtype=torch.float64).contiguous()
         out = torch.empty_like(rhobar)
+        _inputs_ready(self.device, self.stream)
         dG, dtau = ctypes.c_double(), ctypes.c_double()
         _check(library().lbsc_adjoint_backward(self._ctx, ctypes.c_void_p(rhobar.data_ptr()),
                                                ctypes.c_void_p(out.data_ptr()), ctypes.byref(dG),
                                                ctypes.byref(dtau)), self._ctx)
+        _outputs_ready(self.device, self.stream, out, rhobar)
         return out, dG.value, dtau.value
 
     def rate_gradients(self):
@@ -381,6 +414,7 @@ class Batch:
             self._ctx, int(member), ctypes.c_void_p(rho.data_ptr()),
             ctypes.c_void_p(u.data_ptr() if u is not None else 0),
             ctypes.c_void_p(pr.data_ptr() if pr is not None else 0)), self._ctx)
+        _outputs_ready(self.device, self.stream, rho, u, pr)
         return rho, u, pr
 
     def get_state(self, member):

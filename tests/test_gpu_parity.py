@@ -177,6 +177,25 @@ def test_two_kernel_form_is_refused_where_it_does_not_apply():
     b.close()
 
 
+def test_stream_of_its_own_matches_the_current_stream():
+    """A context on a side stream gives the same moments, usable on torch's
+    current stream without an explicit wait."""
+    import torch
+    from paper_1905_09554_amd import lbsc
+    rho0 = gc.ligament(40, 36, 30, 8.0, 0.1, 1, noise=1e-4)
+    prm = lbsc.make_params(40, 36, 30, collision="mrt")
+    a = lbsc.Simulation(rho0, prm)
+    a.step(9)
+    ra, ua, pa = a.moments()
+    side = torch.cuda.Stream()
+    b = lbsc.Simulation(rho0, prm, stream=side)
+    b.step(9)
+    rb, ub, pb = b.moments()
+    assert torch.equal(ra, rb) and torch.equal(ua, ub) and torch.equal(pa, pb)
+    a.close()
+    b.close()
+
+
 def test_zero_steps_is_the_initial_state():
     rho0 = _c1()
     g = gc.run_gpu(rho0, 0)
