@@ -29,6 +29,8 @@ class LigamentRmin(torch.autograd.Function):
         ctx.sim = sim
         ctx.rhobar = rhobar
         ctx.rho0_device = rho0.device
+        # device and shape of each scalar input, for its gradient
+        ctx.scalars = [(v.device, v.shape) for v in (G, tau, s_bulk, s_ghost)]
         return torch.tensor(rmin, dtype=torch.float64)
 
     @staticmethod
@@ -37,11 +39,9 @@ class LigamentRmin(torch.autograd.Function):
         dsb, dsg = ctx.sim.rate_gradients()
         ctx.sim.close()
         g = float(grad_out)
-
-        def t(v):
-            return torch.tensor(v * g, dtype=torch.float64)
-
-        return rho0bar.to(ctx.rho0_device) * g, t(dG), t(dtau), t(dsb), t(dsg), None
+        grads = [torch.full(shape, v * g, dtype=torch.float64, device=dev)
+                 for v, (dev, shape) in zip((dG, dtau, dsb, dsg), ctx.scalars)]
+        return (rho0bar.to(ctx.rho0_device) * g, *grads, None)
 
 
 def ligament_rmin(rho0, G, tau, config, s_bulk=None, s_ghost=None):

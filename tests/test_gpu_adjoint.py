@@ -173,3 +173,25 @@ def test_config5_full_size_adjoint_against_fd():
         # differs from the float64 run by its rounding (observed <= 1.1e-4).
         assert abs(res["f64"][k] - fd[k]) <= 1e-6 * max(abs(fd[k]), 1e-3 * scale), ("f64", k)
         assert abs(res["f32"][k] - fd[k]) <= 5e-4 * max(abs(fd[k]), 1e-3 * scale), ("f32", k)
+
+
+def test_parameter_gradients_follow_their_inputs():
+    """G and tau given as one-element float32 tensors on the GPU get
+    gradients of their own shape and device, equal to the float64 scalar
+    case."""
+    from paper_1905_09554_amd import autograd as lag
+    nx = ny = 16
+    nz, R = 32, 4.0
+    rv, rl = lbm_inputs.coexistence(-5.0)
+    rho0 = torch.from_numpy(lbm_inputs.ligament_density(nx, ny, nz, R, 0.1, 1, rv, rl))
+    cfg = dict(collision="mrt", precision="f64", steps=40, segment=16, rho_v=rv, rho_l=rl)
+    G1 = torch.tensor(-5.0, dtype=torch.float64, requires_grad=True)
+    t1 = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    lag.ligament_rmin(rho0, G1, t1, cfg).backward()
+    G2 = torch.tensor([-5.0], dtype=torch.float32, device="cuda:0", requires_grad=True)
+    t2 = torch.tensor([1.0], dtype=torch.float32, device="cuda:0", requires_grad=True)
+    lag.ligament_rmin(rho0, G2, t2, cfg).backward()
+    for a, b in ((G1, G2), (t1, t2)):
+        assert b.grad.shape == (1,) and b.grad.device.type == "cuda"
+        assert b.grad.dtype == torch.float32
+        assert abs(float(b.grad[0]) - float(a.grad)) <= 1e-6 * abs(float(a.grad))
