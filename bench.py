@@ -325,12 +325,26 @@ def cpu_baseline(rho0, info, nz_sample=16, steps=40):
     for _ in range(steps):
         f = lbm.step(f, p)
     dt = time.perf_counter() - t0
-    return {"value": round(sample.size * steps / dt / 1e6, 3), "unit": "MLUPS",
-            "cores": torch.get_num_threads(), "kind": "oracle", "cpu_model": cpu_model(),
-            "sample": "%dx%dx%d periodic slab (first %d planes of the benchmark input), "
-                      "%s float64, %d steps, %.1f s" % (sample.shape[2], sample.shape[1],
-                                                        nz_sample, nz_sample, info["collision"],
-                                                        steps, dt)}
+    out = {"value": round(sample.size * steps / dt / 1e6, 3), "unit": "MLUPS",
+           "cores": torch.get_num_threads(), "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": "%dx%dx%d periodic slab (first %d planes of the benchmark input), "
+                     "%s float64, %d steps, %.1f s" % (sample.shape[2], sample.shape[1],
+                                                       nz_sample, nz_sample, info["collision"],
+                                                       steps, dt)}
+    # A 20-step window of the 128 x 128 x 512 ligament (first 64 planes), BGK.
+    import lbm_inputs
+    rho2, info2 = lbm_inputs.workload_density("ligament_128x128x512")
+    s2 = rho2[:64].copy()
+    p2 = lbm.Params(G=info2["G"], tau=info2["tau"], collision="bgk")
+    f = lbm.step(lbm.init_rest(torch.from_numpy(s2)), p2)
+    t0 = time.perf_counter()
+    for _ in range(20):
+        f = lbm.step(f, p2)
+    dt2 = time.perf_counter() - t0
+    out["window_128x128x512"] = {
+        "value": round(s2.size * 20 / dt2 / 1e6, 3), "unit": "MLUPS",
+        "sample": "128x128x64 periodic slab (first 64 planes), bgk float64, 20 steps, %.1f s" % dt2}
+    return out
 
 
 def main():
