@@ -94,7 +94,9 @@ typedef struct lbsc_diag {
 typedef struct lbsc_tuning {
   int32_t threads;     /* work-group size of the fused step: 256, 512, 1024   */
   int32_t z_chunk;     /* planes marched per work-group (>= 1)                */
-  int32_t xcd_remap;   /* 1: map neighbouring tiles onto one XCD (L2), 0: off */
+  int32_t xcd_remap;   /* 1: map neighbouring tiles onto one XCD (L2), 0: off;
+                          < 0: the default (1, except 0 for float64 boxes
+                          of more than one wave of work-groups)             */
   int32_t block_y;     /* rows per tile; 0 = as many as the work-group holds  */
   int32_t pop_pad;     /* extra elements between population arrays, <= 65536 */
   int32_t nodes_per_thread; /* interior nodes each thread carries: 1 or 2      */

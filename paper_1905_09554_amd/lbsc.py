@@ -311,7 +311,7 @@ class Simulation:
         return b.value, g.value
 
     # -- launch shape
-    def set_tuning(self, threads=0, z_chunk=0, xcd_remap=1, block_y=0, pop_pad=-1,
+    def set_tuning(self, threads=0, z_chunk=0, xcd_remap=-1, block_y=0, pop_pad=-1,
                    nodes_per_thread=0, persistent=0, block_x=0, two_kernel=0):
         t = Tuning(threads, z_chunk, xcd_remap, block_y, pop_pad, nodes_per_thread, persistent,
                    block_x, two_kernel)
