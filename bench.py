@@ -230,12 +230,12 @@ def run_adjoint():
             "dL_dtau": dtau}
 
 
-def run_small_box(steps=1000, oracle=True):
+def run_small_box(steps=1000):
     """The 32 x 32 x 64 float64 BGK ligament (65 536 nodes, 20 MB of state,
     resident in the last-level cache): the whole run of `steps` steps with
     one launch per step and with one persistent cooperative launch, the time
     of one isolated launch (HIP events around it: kernel plus launch latency,
-    which back-to-back launches hide), and the oracle on the same run."""
+    which back-to-back launches hide)."""
     import torch
     import lbm_inputs
     from paper_1905_09554_amd import lbsc
@@ -279,22 +279,6 @@ def run_small_box(steps=1000, oracle=True):
     torch.cuda.empty_cache()
     out["persistent"] = {"value": round(n * steps / wall_p / 1e6, 1), "unit": "MLUPS",
                          "us_per_step": round(wall_p / steps * 1e6, 2)}
-    if oracle:
-        from oracle import lbm
-        p = lbm.Params(G=info["G"], tau=info["tau"], collision="bgk")
-        nthreads = torch.get_num_threads()
-        res = {}
-        for threads, k in ((min(16, os.cpu_count() or 1), steps), (1, 50)):
-            torch.set_num_threads(threads)
-            f = lbm.step(lbm.init_rest(torch.from_numpy(rho0)), p)
-            t0 = time.perf_counter()
-            for _ in range(k):
-                f = lbm.step(f, p)
-            dt = time.perf_counter() - t0
-            res["threads_%d" % threads] = {"value": round(n * k / dt / 1e6, 3), "unit": "MLUPS",
-                                           "steps": k, "seconds": round(dt, 2)}
-        torch.set_num_threads(nthreads)
-        out["oracle"] = res
     return out
 
 
@@ -344,6 +328,23 @@ def cpu_baseline(rho0, info, nz_sample=16, steps=40):
     out["window_128x128x512"] = {
         "value": round(s2.size * 20 / dt2 / 1e6, 3), "unit": "MLUPS",
         "sample": "128x128x64 periodic slab (first 64 planes), bgk float64, 20 steps, %.1f s" % dt2}
+    # The whole 32 x 32 x 64 BGK box (the small-box figure's run): 1000 steps
+    # on up to 16 threads, 50 steps on one.
+    rho1, info1 = lbm_inputs.workload_density("ligament_32x32x64_bgk_f64")
+    p1 = lbm.Params(G=info1["G"], tau=info1["tau"], collision="bgk")
+    nthreads = torch.get_num_threads()
+    res = {}
+    for threads, k in ((nthreads, 1000), (1, 50)):
+        torch.set_num_threads(threads)
+        f = lbm.step(lbm.init_rest(torch.from_numpy(rho1)), p1)
+        t0 = time.perf_counter()
+        for _ in range(k):
+            f = lbm.step(f, p1)
+        dt1 = time.perf_counter() - t0
+        res["threads_%d" % threads] = {"value": round(rho1.size * k / dt1 / 1e6, 3),
+                                       "unit": "MLUPS", "steps": k, "seconds": round(dt1, 2)}
+    torch.set_num_threads(nthreads)
+    out["small_box_32x32x64"] = res
     return out
 
 
@@ -394,7 +395,7 @@ def main():
         print("adjoint done: ratio %.2f" % adj["ratio"], file=sys.stderr, flush=True)
     small = None
     if not args.no_small:
-        small = run_small_box(oracle=not args.no_cpu_baseline)
+        small = run_small_box()
         print("small box done: %.0f MLUPS per launch, %.0f persistent"
               % (small["per_step_launch"]["value"], small["persistent"]["value"]),
               file=sys.stderr, flush=True)
