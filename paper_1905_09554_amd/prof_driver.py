@@ -7,7 +7,9 @@ Runs the benchmark box (256 x 256 x 1024 ligament, MRT, the launch shape the
 benchmark uses) for a few steps, then a plain device-to-device copy of a known
 size whose counters calibrate FETCH_SIZE and WRITE_SIZE.  With --adjoint it
 runs the adjoint workload instead (64 x 64 x 256 MRT, 4000 steps, checkpoints
-every 200, loss r_min): forward, loss gradient and backward, once.
+every 200, loss r_min): forward, loss gradient and backward, once.  With
+--batch it runs the 64-ligament dispersion batch (3.9e8 nodes, FP32 BGK): 20
+steps with one launch per step, then 20 in one persistent launch.
 """
 import argparse
 import os
@@ -27,11 +29,26 @@ def main():
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--adjoint", action="store_true",
                     help="run the adjoint workload (forward with checkpoints, backward) instead")
+    ap.add_argument("--batch", action="store_true",
+                    help="run the 64-ligament batch instead: 20 steps with one launch per step, "
+                         "then 20 in one persistent launch")
     args = ap.parse_args()
 
     import torch
     import lbm_inputs
     from paper_1905_09554_amd import lbsc, tuning
+
+    if args.batch:
+        from paper_1905_09554_amd import dispersion
+        sweep = dispersion.make_sweep(seed=0)
+        b = dispersion.build_batch(sweep)
+        for mode in (0, 1):
+            b.set_tuning(**dict(b.get_tuning(), persistent=mode))
+            b.step(20)
+            torch.cuda.synchronize()
+        print("batch done", len(sweep["members"]), b.get_tuning(), flush=True)
+        b.close()
+        return
 
     if args.adjoint:
         name = "adjoint_64x64x256_mrt_f32"
