@@ -9,7 +9,8 @@ size whose counters calibrate FETCH_SIZE and WRITE_SIZE.  With --adjoint it
 runs the adjoint workload instead (64 x 64 x 256 MRT, 4000 steps, checkpoints
 every 200, loss r_min): forward, loss gradient and backward, once.  With
 --batch it runs the 64-ligament dispersion batch (3.9e8 nodes, FP32 BGK): 20
-steps with one launch per step, then 20 in one persistent launch.
+steps with one launch per step, then 20 in one persistent launch.  With --small
+it runs the 32 x 32 x 64 FP64 BGK box for 1000 steps, one launch per step.
 """
 import argparse
 import os
@@ -32,11 +33,32 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="run the 64-ligament batch instead: 20 steps with one launch per step, "
                          "then 20 in one persistent launch")
+    ap.add_argument("--small", action="store_true",
+                    help="run the 32 x 32 x 64 FP64 BGK box instead: 1000 steps, one launch each")
     args = ap.parse_args()
 
     import torch
     import lbm_inputs
     from paper_1905_09554_amd import lbsc, tuning
+
+    if args.small:
+        import time
+        name = "ligament_32x32x64_bgk_f64"
+        rho0, info = lbm_inputs.workload_density(name)
+        nz, ny, nx = rho0.shape
+        prm = lbsc.make_params(nx, ny, nz, collision="bgk", precision="f64", G=info["G"],
+                               tau=info["tau"])
+        sim = lbsc.Simulation(rho0, prm)
+        sim.step(20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(1000)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        print("small done", name, "%.2f us per step (wall)" % (wall * 1e3), sim.get_tuning(),
+              flush=True)
+        sim.close()
+        return
 
     if args.batch:
         from paper_1905_09554_amd import dispersion
