@@ -25,8 +25,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
 
-def candidates(nx, precision):
-    """Launch shapes worth timing for a box of row length nx."""
+def candidates(nx, precision, nodes=None):
+    """Launch shapes worth timing for a box of row length nx (and, when
+    given, `nodes` in all: boxes under 16 M nodes also try the short
+    z-chunks that give them enough work-groups)."""
     widths = sorted({nx} | {w for w in (64, 128, 192, 256, 384, 512) if w < nx})
     out = []
     for threads, npt in itertools.product((256, 512, 1024), (1, 2)):
@@ -36,7 +38,10 @@ def candidates(nx, precision):
         for bx in widths:
             if bx > cap or (bx < nx and 2 * bx > cap):
                 continue  # split rows only as tiles of two or more rows
-            for zc in (16, 32, 64, 128, 256):
+            chunks = (16, 32, 64, 128, 256)
+            if nodes is not None and nodes < (1 << 24):
+                chunks = (1, 2, 4, 8) + chunks
+            for zc in chunks:
                 out.append(dict(threads=threads, nodes_per_thread=npt, block_x=bx, z_chunk=zc))
     return out
 
@@ -82,7 +87,7 @@ def tune(workload, precision, collision, steps=20, progress=True, out=None, box=
     sim = lbsc.Simulation(rho0, prm)
     default_shape = sim.get_tuning()
     tried = []
-    for c in candidates(nx, precision):
+    for c in candidates(nx, precision, nodes=n):
         for remap in (1, 0):
             try:
                 sim.set_tuning(xcd_remap=remap, **c)

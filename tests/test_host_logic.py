@@ -24,9 +24,11 @@ def test_tau_for_ohnesorge_inverts_eq_oh_tcap():
 
 def test_autotune_candidates_are_valid_shapes():
     from paper_1905_09554_amd import autotune
-    for nx, prec in ((256, "f32"), (256, "f64"), (32, "f64"), (600, "f32")):
-        cands = autotune.candidates(nx, prec)
+    for nx, prec, nodes in ((256, "f32", None), (256, "f64", None), (32, "f64", 65536),
+                            (600, "f32", None)):
+        cands = autotune.candidates(nx, prec, nodes=nodes)
         assert cands
+        assert any(c["z_chunk"] < 16 for c in cands) == (nodes is not None)
         for c in cands:
             cap = c["threads"] * c["nodes_per_thread"]
             assert c["block_x"] <= min(nx, cap)
