@@ -165,6 +165,37 @@ def run_two_kernel(rho0, info, precision, reps=100):
             "values_per_node": 59, "dtype": precision}
 
 
+def run_accuracy(rho0, info, steps=1000):
+    """FP32 shifted storage against FP64 on the benchmark box: both from the
+    same input for `steps` steps, then the largest relative density error
+    and the largest velocity (u^b) error over all nodes.  The FP64 step is
+    the reference (it matches the oracle to 1e-12, on sampled nodes at this
+    size)."""
+    import torch
+    from paper_1905_09554_amd import lbsc
+
+    nz, ny, nx = rho0.shape
+    res = {}
+    for prec in ("f64", "f32"):
+        prm = lbsc.make_params(nx, ny, nz, collision=info["collision"], precision=prec,
+                               G=info["G"], tau=info["tau"], rho_ref=1.0)
+        sim = lbsc.Simulation(rho0, prm, device="cuda:0")
+        sim.step(steps)
+        rho, u, _ = sim.moments(want_p=False)
+        torch.cuda.synchronize()
+        sim.close()
+        del sim
+        res[prec] = (rho, u)
+    (r64, u64), (r32, u32) = res["f64"], res["f32"]
+    out = {"steps": steps, "reference": "f64 step on the GPU",
+           "max_rel_drho": float(((r32 - r64).abs() / r64).max()),
+           "max_abs_du": float((u32 - u64).abs().max()),
+           "max_abs_u": float(u64.abs().max())}
+    del res, r64, u64, r32, u32
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_batch(steps, warmup):
     """The 64-ligament dispersion sweep (uneven boxes, 3.9e8 nodes) in one
     batch: MLUPS with one launch per step and with one persistent launch."""
@@ -360,6 +391,8 @@ def main():
     ap.add_argument("--no-small", action="store_true", help="skip the 32x32x64 small-box figure")
     ap.add_argument("--no-two-kernel", action="store_true",
                     help="skip the unfused two-kernel baseline figure")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the FP32-against-FP64 error after 1000 steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the step is single-GPU; see the design notes "
@@ -386,6 +419,10 @@ def main():
         two["fused_kernel_ms"] = round(f32["kernel_ms"], 4)
         two["fused_speedup"] = round(two["kernel_ms"] / f32["kernel_ms"], 3)
         print("two-kernel done: %.3f ms per step" % two["kernel_ms"], file=sys.stderr, flush=True)
+    acc = None
+    if not args.no_accuracy:
+        acc = run_accuracy(rho0, info)
+        print("accuracy done: max rel drho %.2e" % acc["max_rel_drho"], file=sys.stderr, flush=True)
     batch = None
     if not args.no_batch:
         batch = run_batch(max(20, args.steps // 5), 5)
@@ -440,6 +477,8 @@ def main():
                         "value_kernel_only": round(rho0.size / (f64["kernel_ms"] * 1e-3) / 1e6, 1),
                         "mass_drift_per_1000": f64["mass_drift_per_1000"],
                         "tuning": f64["tuning"]}
+    if acc:
+        line["fp32_vs_fp64"] = acc
     if two:
         line["two_kernel_baseline"] = two
     if batch:
