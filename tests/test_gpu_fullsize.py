@@ -59,3 +59,31 @@ def test_full_size_sampled(name, coll, prec, steps, kR):
         r_ref, u_ref = gc.oracle_at_node(rho0, node, steps, coll, G=info["G"], tau=info["tau"])
         assert abs(rho_s[k] - r_ref) <= rtol * r_ref, (node, rho_s[k], r_ref)
         assert float(np.abs(u_s[:, k] - u_ref).max()) <= utol, (node, u_s[:, k], u_ref)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_two_kernel_form_full_size_bitwise(prec):
+    """The benchmark box in the two-kernel form: density and velocity after
+    3 steps equal the fused kernel's bitwise (same arithmetic, psi through
+    global memory instead of LDS)."""
+    from paper_1905_09554_amd import lbsc
+    name = "ligament_256x256x1024_mrt_f32"
+    rho0, info = lbm_inputs.workload_density(name)
+    nz, ny, nx = rho0.shape
+    print("two-kernel full size %s %s" % (name, prec), flush=True)
+    prm = lbsc.make_params(nx, ny, nz, collision=info["collision"], precision=prec, G=info["G"],
+                           tau=info["tau"])
+    out = []
+    for two in (0, 1):
+        sim = lbsc.Simulation(rho0, prm)
+        if two:
+            sim.set_tuning(two_kernel=1)
+        sim.step(3)
+        rho, u, _ = sim.moments(want_p=False)
+        torch.cuda.synchronize()
+        sim.close()
+        out.append((rho, u))
+        del sim
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    del out
+    torch.cuda.empty_cache()
