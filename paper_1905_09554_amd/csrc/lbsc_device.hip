@@ -492,7 +492,11 @@ __device__ inline void step_tile(const T* __restrict__ src, T* __restrict__ dst,
 
   for (int z = z0, it = 0; z < z1; ++z, ++it) {
     const int znext = z == nz - 1 ? 0 : z + 1;
+    // The next plane's loads go out at raised wave priority, so that a
+    // work-group issuing them is not held back by another's collision.
+    __builtin_amdgcn_s_setprio(2);
     load_plane(znext, (it + 2) & 3, nxt);
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();
     const R* pm = lds + (it & 3) * lplane;
     const R* pc = lds + ((it + 1) & 3) * lplane;
