@@ -250,6 +250,12 @@ int lbsc_adjoint_rate_gradients(const lbsc_ctx* c, double* dL_ds_bulk, double* d
 int lbsc_set_tuning(lbsc_ctx* c, const lbsc_tuning* t);
 int lbsc_get_tuning(const lbsc_ctx* c, lbsc_tuning* t);
 
+/* The launch shape a context for these n boxes starts with, as
+ * lbsc_get_tuning would report it (for a single box: the effective tile,
+ * chunk and padding).  Host only: needs no GPU and no context.  Returns
+ * LBSC_EINVAL for invalid parameters or a NULL t. */
+int lbsc_default_tuning(const lbsc_params* p, int32_t n, lbsc_tuning* t);
+
 /* Lattice of the library: velocities c[19][3] (cx, cy, cz) and weights w[19]
  * in the population order used by lbsc_get_state.  Either may be NULL. */
 void lbsc_lattice(int32_t* c, double* w);

@@ -809,6 +809,21 @@ int lbsc_get_tuning(const lbsc_ctx* c, lbsc_tuning* t) {
   return LBSC_OK;
 }
 
+int lbsc_default_tuning(const lbsc_params* p, int32_t n, lbsc_tuning* t) {
+  if (!t || check_batch(n, p, nullptr) != LBSC_OK) return LBSC_EINVAL;
+  *t = default_tuning(p, n);
+  if (n == 1) {
+    // As lbsc_get_tuning reports it for a single box: the effective tile and
+    // chunk, and the population padding.
+    const lbsc::StepArgs a = make_args(p[0], *t, kDefaultPad);
+    t->block_x = a.bx;
+    t->block_y = a.by;
+    t->z_chunk = a.zchunk;
+    t->pop_pad = (int32_t)(a.ps - (a.n + 63) / 64 * 64);
+  }
+  return LBSC_OK;
+}
+
 size_t lbsc_adjoint_workspace_bytes(const lbsc_params* p, int64_t nsteps, int32_t segment) {
   if (check_adjoint(p, nsteps, segment, nullptr) != LBSC_OK) return 0;
   return adj_layout(*p, nsteps, segment).total;

@@ -84,6 +84,7 @@ def library():
             "lbsc_set_state": (ctypes.c_int, [vp, vp, sz, i64]),
             "lbsc_set_tuning": (ctypes.c_int, [vp, P(Tuning)]),
             "lbsc_get_tuning": (ctypes.c_int, [vp, P(Tuning)]),
+            "lbsc_default_tuning": (ctypes.c_int, [P(Params), i32, P(Tuning)]),
             "lbsc_lattice": (None, [P(i32), P(dbl)]),
             "lbsc_adjoint_workspace_bytes": (sz, [P(Params), i64, i32]),
             "lbsc_adjoint_forward": (ctypes.c_int, [vp, i64, i32, vp, sz]),
@@ -116,6 +117,16 @@ def make_params(nx, ny, nz, collision="bgk", forcing="guo", precision="f64", G=-
 
 def state_bytes(params):
     return library().lbsc_state_bytes(ctypes.byref(params))
+
+
+def default_tuning(params):
+    """The launch shape a context starts with (host only, no GPU): a dict
+    like Simulation.get_tuning() for one Params, or a batch's for a list."""
+    plist = list(params) if isinstance(params, (list, tuple)) else [params]
+    arr = (Params * len(plist))(*plist)
+    t = Tuning()
+    _check(library().lbsc_default_tuning(arr, len(plist), ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in Tuning._fields_}
 
 
 def lattice():

@@ -151,3 +151,28 @@ def test_binding_structs_match_the_header_layout(tmp_path):
     body = re.search(r"typedef struct lbsc_tuning \{(.*?)\} lbsc_tuning;", text, flags=re.S).group(1)
     declared = re.findall(r"\b(\w+)\s*;", body)
     assert declared == [f for f, _ in lbsc.Tuning._fields_]
+
+
+@pytest.mark.parametrize("box,coll,prec,expect", [
+    # (threads, block_x, block_y, z_chunk, xcd_remap)
+    ((256, 256, 1024), "mrt", "f32", (1024, 256, 4, 256, 1)),   # one wave of 256 groups
+    ((256, 256, 1024), "mrt", "f64", (256, 64, 4, 64, 0)),      # eight waves: dispatch order
+    ((128, 128, 512), "bgk", "f64", (256, 64, 4, 64, 1)),       # one wave: XCD-local ranges
+    ((64, 64, 256), "mrt", "f32", (1024, 64, 16, 4, 1)),
+    ((32, 32, 64), "bgk", "f64", (256, 32, 8, 1, 1)),           # small box: one-plane chunks
+    ((384, 384, 1024), "mrt", "f32", (512, 128, 4, 64, 1)),     # rows wider than 256 nodes
+])
+def test_default_launch_shapes(box, coll, prec, expect):
+    """The library's default launch shape (host only) for the boxes whose
+    measurements chose the policy."""
+    nx, ny, nz = box
+    t = lbsc.default_tuning(_params(nx=nx, ny=ny, nz=nz, collision=coll, precision=prec))
+    got = (t["threads"], t["block_x"], t["block_y"], t["z_chunk"], t["xcd_remap"])
+    assert got == expect
+    assert t["block_x"] * t["block_y"] <= t["threads"] * t["nodes_per_thread"]
+    assert t["persistent"] == 0 and t["two_kernel"] == 0
+
+
+def test_default_tuning_rejects_invalid_parameters():
+    with pytest.raises(lbsc.LbscError):
+        lbsc.default_tuning(_params(tau=0.5))

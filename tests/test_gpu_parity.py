@@ -196,6 +196,17 @@ def test_stream_of_its_own_matches_the_current_stream():
     b.close()
 
 
+@pytest.mark.parametrize("box,coll,prec", [((40, 36, 30), "mrt", "f32"), ((150, 24, 10), "bgk", "f64"),
+                                           ((32, 32, 64), "bgk", "f64")])
+def test_context_starts_with_the_host_default_tuning(box, coll, prec):
+    from paper_1905_09554_amd import lbsc
+    nx, ny, nz = box
+    prm = lbsc.make_params(nx, ny, nz, collision=coll, precision=prec)
+    sim = lbsc.Simulation(gc.ligament(nx, ny, nz, 6.0, 0.1, 1), prm)
+    assert sim.get_tuning() == lbsc.default_tuning(prm)
+    sim.close()
+
+
 def test_zero_steps_is_the_initial_state():
     rho0 = _c1()
     g = gc.run_gpu(rho0, 0)
