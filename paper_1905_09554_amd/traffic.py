@@ -46,6 +46,28 @@ def _per_kernel(rows):
     return statistics.mean(step), copy[-1], len(step)
 
 
+def reduce_counters(fetch_rows, write_rows, precision, nodes):
+    """Per-launch bytes of the step kernel from (kernel name, KiB) rows of the
+    two counters, each scaled by its reading for the plain copy."""
+    f_step, f_copy, nf = _per_kernel(fetch_rows)
+    w_step, w_copy, nw = _per_kernel(write_rows)
+    kib = COPY_BYTES / 1024.0
+    f_scale, w_scale = kib / f_copy, kib / w_copy
+    fetch_b = f_step * f_scale * 1024.0
+    write_b = w_step * w_scale * 1024.0
+    elem = 4 if precision == "f32" else 8
+    alg = 19 * elem * nodes
+    return {
+        "fetch_kib_raw": f_step, "write_kib_raw": w_step, "dispatches": [nf, nw],
+        "copy_fetch_kib": f_copy, "copy_write_kib": w_copy,
+        "fetch_scale": f_scale, "write_scale": w_scale,
+        "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
+        "bytes_per_launch": fetch_b + write_b,
+        "algorithmic_bytes_per_launch": 2 * alg,
+        "fetch_over_algorithmic": fetch_b / alg, "write_over_algorithmic": write_b / alg,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--fetch", required=True)
@@ -59,26 +81,13 @@ def main():
     sys.path.insert(0, ROOT)
     from bench import kernel_source_hash, launch_shape_entry
 
-    f_step, f_copy, nf = _per_kernel(_rows(args.fetch, "FETCH_SIZE"))
-    w_step, w_copy, nw = _per_kernel(_rows(args.write, "WRITE_SIZE"))
-    kib = COPY_BYTES / 1024.0
-    f_scale, w_scale = kib / f_copy, kib / w_copy
-    fetch_b = f_step * f_scale * 1024.0
-    write_b = w_step * w_scale * 1024.0
-    elem = 4 if args.precision == "f32" else 8
-    alg = 19 * elem * args.nodes
     rec = {
         "workload": args.workload, "precision": args.precision, "nodes": args.nodes,
         "source_hash": kernel_source_hash(),
         "launch_shape": launch_shape_entry(args.workload, args.precision),
-        "fetch_kib_raw": f_step, "write_kib_raw": w_step, "dispatches": [nf, nw],
-        "copy_fetch_kib": f_copy, "copy_write_kib": w_copy,
-        "fetch_scale": f_scale, "write_scale": w_scale,
-        "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
-        "bytes_per_launch": fetch_b + write_b,
-        "algorithmic_bytes_per_launch": 2 * alg,
-        "fetch_over_algorithmic": fetch_b / alg, "write_over_algorithmic": write_b / alg,
     }
+    rec.update(reduce_counters(_rows(args.fetch, "FETCH_SIZE"), _rows(args.write, "WRITE_SIZE"),
+                               args.precision, args.nodes))
     out = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (args.workload, args.precision))
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)

@@ -1,6 +1,7 @@
 """Host-side logic of the drivers, without a GPU: fits, closed forms, launch
 shape candidates, observable bookkeeping and input builders."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -138,3 +139,42 @@ def test_drop_segmentation_and_satellites():
     # a satellite that outlives the run is counted up to the last sample
     s = breakup.satellites([(0, [big]), (100, [big, sat]), (400, [big, sat])], info)
     assert abs(s["life_tcap"] - 3.0) < 1e-12
+
+
+def test_counter_reduction_scales_by_the_copy(tmp_path):
+    """traffic.py on synthetic rocprofv3 counter files: the copy's reading
+    calibrates each counter (FETCH_SIZE reads half a copy's bytes), and the
+    step kernel's per-launch bytes follow."""
+    import csv as _csv
+    from paper_1905_09554_amd import traffic
+    from paper_1905_09554_amd.prof_driver import COPY_BYTES
+    kib = COPY_BYTES / 1024.0
+    nodes = 1000
+    for counter, copy_val, step_val in (("FETCH_SIZE", kib / 2, 80.0), ("WRITE_SIZE", kib, 75.0)):
+        d = tmp_path / counter
+        d.mkdir()
+        with open(d / "run_counter_collection.csv", "w", newline="") as fh:
+            w = _csv.DictWriter(fh, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+            w.writeheader()
+            for v in (step_val - 1, step_val + 1):
+                w.writerow({"Kernel_Name": "void k_step<float, 1, 0, 1024, 1>(...)",
+                            "Counter_Name": counter, "Counter_Value": v})
+            w.writerow({"Kernel_Name": "__amd_rocclr_copyBuffer", "Counter_Name": counter,
+                        "Counter_Value": copy_val})
+    rec = traffic.reduce_counters(traffic._rows(str(tmp_path / "FETCH_SIZE"), "FETCH_SIZE"),
+                                  traffic._rows(str(tmp_path / "WRITE_SIZE"), "WRITE_SIZE"),
+                                  "f32", nodes)
+    assert rec["dispatches"] == [2, 2]
+    assert rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0
+    assert rec["fetch_bytes_per_launch"] == 80.0 * 2 * 1024
+    assert rec["write_bytes_per_launch"] == 75.0 * 1024
+    assert rec["algorithmic_bytes_per_launch"] == 2 * 19 * 4 * nodes
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
