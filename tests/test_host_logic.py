@@ -178,3 +178,13 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_stale_counter_files_are_ignored(monkeypatch):
+    """The benchmark uses the committed counter files only for the kernel
+    sources and launch shape they were taken with."""
+    import bench
+    for prec in ("f32", "f64"):
+        monkeypatch.setattr(bench, "kernel_source_hash", lambda: "not-these-sources")
+        assert bench.measured_traffic(bench.WORKLOAD, prec) is None
+        monkeypatch.undo()
