@@ -226,6 +226,27 @@ long long tile_columns(const lbsc_params* p, int32_t n, int threads) {
   return columns;
 }
 
+// Default chunk length and tile order for work-groups of t->threads.
+void chunk_and_order(const lbsc_params* p, int32_t n, lbsc_tuning* t) {
+  // Chunk length.  A single box on 1024-thread groups: one wave of 256 groups,
+  // one per CU (no tail), up to 256 planes.  Otherwise about 512 groups of 1
+  // to 64 planes: long marches keep the two extra halo planes of each chunk a
+  // small fraction on large boxes, short ones give small boxes enough groups.
+  const long long columns = tile_columns(p, n, t->threads);
+  const bool one_wave = t->threads == 1024 && n == 1;
+  const long long groups = one_wave ? 256 : 512;
+  const long long zmax = one_wave ? 256 : 64;
+  long long zc = (columns + groups - 1) / groups;
+  if (zc < 1) zc = 1;
+  if (zc > zmax) zc = zmax;
+  t->z_chunk = (int)zc;
+  // float64 over more than one wave of groups (two 256-thread groups per CU):
+  // plain dispatch order beats XCD-local tile ranges (measured 14.15 against
+  // 13.87 GLUPS on 256 x 256 x 1024 MRT, eight waves); within one wave the
+  // XCD-local ranges win (32 x 32 x 64: 7.2 against 5.9 GLUPS).
+  t->xcd_remap = (p[0].precision == LBSC_F64 && (columns + zc - 1) / zc > 512) ? 0 : 1;
+}
+
 lbsc_tuning default_tuning(const lbsc_params* p, int32_t n) {
   lbsc_tuning t;
   t.block_x = 0;
@@ -259,23 +280,7 @@ lbsc_tuning default_tuning(const lbsc_params* p, int32_t n) {
   } else {
     t.threads = 256;
   }
-  // Chunk length.  A single box on 1024-thread groups: one wave of 256 groups,
-  // one per CU (no tail), up to 256 planes.  Otherwise about 512 groups of 1
-  // to 64 planes: long marches keep the two extra halo planes of each chunk a
-  // small fraction on large boxes, short ones give small boxes enough groups.
-  const long long columns = tile_columns(p, n, t.threads);
-  const bool one_wave = t.threads == 1024 && n == 1;
-  const long long groups = one_wave ? 256 : 512;
-  const long long zmax = one_wave ? 256 : 64;
-  long long zc = (columns + groups - 1) / groups;
-  if (zc < 1) zc = 1;
-  if (zc > zmax) zc = zmax;
-  t.z_chunk = (int)zc;
-  // float64 over more than one wave of groups (two 256-thread groups per CU):
-  // plain dispatch order beats XCD-local tile ranges (measured 14.15 against
-  // 13.87 GLUPS on 256 x 256 x 1024 MRT, eight waves); within one wave the
-  // XCD-local ranges win (32 x 32 x 64: 7.2 against 5.9 GLUPS).
-  if (p[0].precision == LBSC_F64 && (columns + zc - 1) / zc > 512) t.xcd_remap = 0;
+  chunk_and_order(p, n, &t);
   return t;
 }
 
@@ -746,6 +751,8 @@ int lbsc_set_tuning(lbsc_ctx* c, const lbsc_tuning* t) {
     if (t->threads != 256 && t->threads != 512 && t->threads != 1024)
       return fail(&c->err, LBSC_EINVAL, "threads must be 256, 512 or 1024");
     n.threads = t->threads;
+    // The default chunk and tile order are those of the requested group size.
+    chunk_and_order(ps.data(), (int32_t)ps.size(), &n);
   }
   if (t->z_chunk < 0 || t->block_y < 0 || t->block_x < 0)
     return fail(&c->err, LBSC_EINVAL, "negative tuning value");
