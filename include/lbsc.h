@@ -87,10 +87,12 @@ typedef struct lbsc_diag {
  * threads, z_chunk, block_y, nodes_per_thread, block_x: 0 means the default;
  * pop_pad < 0 means the default.  A tile of the fused step is block_x columns
  * by block_y rows (block_x * block_y <= nodes_per_thread * threads); the
- * default block_x is the whole row when the work-group holds two or more
- * rows and 2 nx <= threads, else the widest multiple of 64 whose tile and
- * halo ring (2 (block_x + 2) + 2 block_y nodes) fit the work-group.  Changing pop_pad re-lays the state out in
- * place (same values). */
+ * default block_x is the whole row when the work-group holds at least
+ * min_rows rows (4 for float64, for 1024-thread groups and for rows wider
+ * than half the group; 2 otherwise) and 2 nx <= threads, else the widest
+ * multiple of 64 whose tile and halo ring (2 (block_x + 2) + 2 block_y nodes)
+ * fit the work-group.  lbsc_default_tuning gives the whole default on the
+ * host.  Changing pop_pad re-lays the state out in place (same values). */
 typedef struct lbsc_tuning {
   int32_t threads;     /* work-group size of the fused step: 256, 512, 1024   */
   int32_t z_chunk;     /* planes marched per work-group (>= 1)                */
@@ -112,7 +114,8 @@ typedef struct lbsc_tuning {
 /* Bytes of device memory a context with these parameters needs: two
  * population lattices of 19 arrays of nx * ny * nz values in the storage
  * precision (each array padded by up to 65536 elements so the arrays do not
- * share HBM channels), plus a reduction area.  Returns 0 for invalid
+ * share HBM channels), plus a reduction area and the psi field of the
+ * two-kernel form of the step (nx * ny * nz values).  Returns 0 for invalid
  * parameters. */
 size_t lbsc_state_bytes(const lbsc_params* p);
 
