@@ -13,10 +13,14 @@
                  position and is piecewise differentiable.
 * velocity magnitude v* = |u^b| / (R0 / t_cap)                    (Sec. 4, Fig. 6)
 
-Pins: r(z) of an exactly cylindrical step profile recovers the cylinder area;
-pressure of a uniform state equals Eq. EOS_SC term by term is NOT a pin (that
-would restate the formula); the EoS is pinned through the flat-interface
-coexistence and the Laplace law in the physics tests.
+Pins (tests/test_oracle_diagnostics.py): the liquid area of a sharp disc
+slice is its lattice-node count and its equivalent radius is the disc radius
+to O(1/R) (Gauss circle count); a tanh wall of width W adds pi^3 W^2 / 48 to
+the area (closed form); densities above rho_l count 1, below rho_v 0, the mid
+density 1/2; equal minima go to the smallest z; a state at rest has zero
+momentum; v* of a uniform flow is |u| t_cap / R0.  The pressure is not pinned
+by restating Eq. EOS_SC: the EoS is pinned through the flat-interface
+coexistence densities and the Laplace law (tests/test_oracle_physics.py).
 """
 import math
 

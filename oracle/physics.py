@@ -15,9 +15,13 @@
   omega t_cap = 0.2800 at kR0 ~ 0.687, Oh = 0.1; the approximation gives
   0.289 there.
 
-Pins: the Laplace slope against Table 2's sigma (tests/test_oracle_physics.py);
-the Weber rate against the paper's 0.2800 within 4 % and its closed-form
-limits (inviscid x^2 (1 - x^2) / 2, zero at x = 1).
+Pins (tests/test_oracle_diagnostics.py, tests/test_oracle_physics.py):
+laplace_sigma itself at G0 = -5.3 against Table 2's sigma within 5 %, with
+Delta P linear in 1/R; capillary_time against the t_cap rows of Tables 1 and 2
+(uniformly 1.5 % below the printed values, a constant offset of the tables);
+ohnesorge against Table 2's Oh = 0.1 and the closed form Oh t_cap = mu R0 /
+sigma; the Weber rate against the paper's 0.2800 within 4 % and its
+closed-form limits (inviscid x^2 (1 - x^2) / 2, zero at x = 1).
 """
 import math
 
@@ -50,11 +54,12 @@ def cylinder_pressure_jump(R, G, rho_v, rho_l, n=64, collision="mrt", tau=1.0, t
 
 
 def laplace_sigma(G, rho_v, rho_l, radii=(8, 12, 16), **kw):
-    """(sigma, intercept) of Delta P = sigma / R + c over the given radii."""
+    """(sigma, intercept, jumps): least-squares fit of Delta P = sigma / R + c
+    over the given radii, and the jumps Delta P(R) it was fitted to."""
     dps = [cylinder_pressure_jump(R, G, rho_v, rho_l, **kw) for R in radii]
     A = np.array([[1.0 / R, 1.0] for R in radii])
     (sigma, icpt), _, _, _ = np.linalg.lstsq(A, np.array(dps), rcond=None)
-    return float(sigma), float(icpt)
+    return float(sigma), float(icpt), dps
 
 
 def kinematic_viscosity(tau):

@@ -38,7 +38,7 @@ def main():
         out["%.4f" % G] = flat_run(G)
         rec = out["%.4f" % G]
         # Surface tension from the Laplace law of static cylinders (MRT).
-        sigma, icpt = physics.laplace_sigma(G, rec["rho_v"], rec["rho_l"])
+        sigma, icpt, _ = physics.laplace_sigma(G, rec["rho_v"], rec["rho_l"])
         rec["sigma_laplace"] = {"sigma": sigma, "intercept": icpt, "radii": [8, 12, 16],
                                 "box": "64x64x1", "collision": "mrt", "tau": 1.0}
         print(G, rec)
