@@ -155,6 +155,26 @@ int lbsc_compute_moments(lbsc_ctx* c, double* rho_dev, double* u_dev, double* p_
 int lbsc_interface_diagnostics(lbsc_ctx* c, double rho_v, double rho_l, lbsc_diag* out,
                                double* r_of_z_host);
 
+/* For callers that cannot allocate device memory at the time of the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): lbsc_interface_diagnostics with its reduction scratch -- the
+ * per-block partial sums and the results -- in a static device array of the
+ * library instead of the context's buffer.  Same arguments, kernels and
+ * results (bitwise) as lbsc_interface_diagnostics; the density and psi fields
+ * still use the context's idle lattice, as there.  Calls no hipMalloc,
+ * hipFree or other allocating routine.
+ *   Limit: the array holds 16 MiB per GPU, for the life of the process; a box
+ *   needs nz * ceil(nx * ny / 4096) * 64 bytes of partials plus
+ *   (4 + nz) * 8 bytes of results (rounded up to 256 bytes), so e.g.
+ *   672 x 672 x 1792 fits; larger boxes return LBSC_EINVAL.
+ *   The context's device must be current (LBSC_EINVAL otherwise).
+ *   Every call on one GPU shares that GPU's array: calls that overlap in
+ *   time on one GPU (other host threads, other streams) race and must be
+ *   serialised by the caller.  Each call writes every value it reads, so
+ *   nothing needs clearing between calls.  Synchronises the stream. */
+int lbsc_interface_diagnostics_static(lbsc_ctx* c, double rho_v, double rho_l, lbsc_diag* out,
+                                      double* r_of_z_host);
+
 /* Copies the post-streaming populations f_a(x) of the current time step to
  * host memory: 19*N values [a][z][y][x] in the storage precision (float64 f,
  * or float32 g = f - w rho_ref), bytes = 19*N*size.  *step receives the step

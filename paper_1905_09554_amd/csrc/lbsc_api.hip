@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -62,6 +63,7 @@ struct AdjWork {
 struct lbsc_ctx {
   std::vector<Member> m;
   bool batch;
+  int device;                    // HIP device holding the caller's buffer
   lbsc_tuning tune;
   hipStream_t stream;
   char* buf;
@@ -94,6 +96,34 @@ constexpr unsigned kSpinLimit = 1u << 23;
 // Narrowest tile that does not span a whole row (one wavefront of columns);
 // bounds the size of the tile table.
 constexpr int kMinBlockX = 64;
+
+// Device scratch of lbsc_interface_diagnostics_static, for callers that
+// cannot allocate: the diagnostic results (4 + nz doubles) and the per-block
+// partial sums (8 doubles per block), 16 MiB in all.  Each GPU holds its own
+// copy for the life of the process.  Host code never passes `scratch` itself
+// to a kernel (on the host it only names the variable): it passes the
+// device address that hipGetSymbolAddress returned for the current device,
+// resolved once per device when the first context is created there.
+constexpr size_t kScratchDoubles = size_t(1) << 21;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Resolves the scratch address of device `dev` (the current device) once.
+hipError_t resolve_scratch(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[dev]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) g_scratch_dev[dev] = static_cast<double*>(ptr);
+  return e;
+}
+
+double* scratch_of(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_dev[dev];
+}
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 size_t elem_size(const lbsc_params& p) { return p.precision == LBSC_F64 ? 8 : 4; }
@@ -397,10 +427,29 @@ int create(lbsc_ctx** out, int32_t n, const lbsc_params* p, const double* const*
     (void)hipGetLastError();
     return fail(&g_init_err, LBSC_EINVAL, "dev_buf is not device memory");
   }
+  // The device that holds the buffer; its copy of the static scratch is
+  // resolved with it current.
+  const int dev = attr.device;
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(&g_init_err, LBSC_EINVAL, "dev_buf is on an unsupported device index");
+  {
+    int prev = -1;
+    hipError_t e = hipGetDevice(&prev);
+    if (e == hipSuccess && prev != dev) e = hipSetDevice(dev);
+    if (e == hipSuccess) e = resolve_scratch(dev);
+    if (prev >= 0 && prev != dev) {
+      const hipError_t e2 = hipSetDevice(prev);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess)
+      return fail(&g_init_err, LBSC_EHIP,
+                  std::string("device scratch address: ") + hipGetErrorString(e));
+  }
 
   lbsc_ctx* c = new (std::nothrow) lbsc_ctx();
   if (!c) return fail(&g_init_err, LBSC_ENOMEM, "context allocation failed");
   c->batch = batch;
+  c->device = dev;
   c->tune = default_tuning(p, n);
   c->stream = (hipStream_t)hip_stream;
   c->buf = (char*)dev_buf;
@@ -521,18 +570,21 @@ int moments_of(lbsc_ctx* c, Member* mm, double* rho_dev, double* u_dev, double* 
   return LBSC_OK;
 }
 
-int diagnostics_of(lbsc_ctx* c, Member* mm, double rho_v, double rho_l, lbsc_diag* out,
-                   double* r_of_z_host) {
+// Interface diagnostics of member mm with the reduction partials and the
+// results in `part` and `dres` (the context's aux area, or the static
+// scratch); rho and psi go to the idle lattice.
+int diagnostics_into(lbsc_ctx* c, Member* mm, double rho_v, double rho_l, lbsc_diag* out,
+                     double* r_of_z_host, double* part, double* dres) {
   if (!out) return fail(&c->err, LBSC_EINVAL, "out is NULL");
   if (!(std::isfinite(rho_v) && std::isfinite(rho_l) && rho_l > rho_v))
     return fail(&c->err, LBSC_EINVAL, "need finite rho_l > rho_v");
   const int nz = mm->p.nz;
   hipError_t e = lbsc::launch_diagnostics(mm->p.precision, mm->lat[c->cur],
-                                          (double*)mm->lat[c->cur ^ 1], c->part, c->dout, rho_v,
+                                          (double*)mm->lat[c->cur ^ 1], part, dres, rho_v,
                                           rho_l, mm->a, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "diagnostics launch");
   std::vector<double> h(4 + (size_t)nz);
-  HIP_OR_FAIL(c, hipMemcpyAsync(h.data(), c->dout, h.size() * sizeof(double),
+  HIP_OR_FAIL(c, hipMemcpyAsync(h.data(), dres, h.size() * sizeof(double),
                                 hipMemcpyDeviceToHost, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   out->mass = h[0];
@@ -555,6 +607,11 @@ int diagnostics_of(lbsc_ctx* c, Member* mm, double rho_v, double rho_l, lbsc_dia
   out->z_argmin = zmin;
   if (!std::isfinite(h[0])) return fail(&c->err, LBSC_ENONFINITE, "mass is not finite");
   return LBSC_OK;
+}
+
+int diagnostics_of(lbsc_ctx* c, Member* mm, double rho_v, double rho_l, lbsc_diag* out,
+                   double* r_of_z_host) {
+  return diagnostics_into(c, mm, rho_v, rho_l, out, r_of_z_host, c->part, c->dout);
 }
 
 int get_state_of(lbsc_ctx* c, Member* mm, void* host, size_t bytes) {
@@ -705,6 +762,26 @@ int lbsc_member_diagnostics(lbsc_ctx* c, int32_t i, double rho_v, double rho_l, 
   Member* mm = member(c, i);
   if (!mm) return LBSC_EINVAL;
   return diagnostics_of(c, mm, rho_v, rho_l, out, r_of_z_host);
+}
+
+int lbsc_interface_diagnostics_static(lbsc_ctx* c, double rho_v, double rho_l, lbsc_diag* out,
+                                      double* r_of_z_host) {
+  Member* mm = member(c, 0);
+  if (!mm) return LBSC_EINVAL;
+  int dev = -1;
+  HIP_OR_FAIL(c, hipGetDevice(&dev));
+  if (dev != c->device) return fail(&c->err, LBSC_EINVAL, "the context's device must be current");
+  double* base = scratch_of(dev);
+  if (!base) return fail(&c->err, LBSC_ESTATE, "device scratch address not resolved");
+  // Results first, then the partials from a 256-byte boundary.
+  const size_t res = ((size_t)(4 + mm->p.nz) + 31) / 32 * 32;
+  const size_t need = res + 8 * (size_t)lbsc::diag_blocks(mm->a);
+  if (need > kScratchDoubles)
+    return fail(&c->err, LBSC_EINVAL,
+                "box too large for the static scratch: needs " + std::to_string(need * 8) +
+                    " bytes of " + std::to_string(kScratchDoubles * 8) +
+                    " (nz * ceil(nx * ny / 4096) * 64 + (4 + nz) * 8 bytes, rounded)");
+  return diagnostics_into(c, mm, rho_v, rho_l, out, r_of_z_host, base + res, base);
 }
 
 int lbsc_get_state(lbsc_ctx* c, void* host, size_t bytes, int64_t* step) {

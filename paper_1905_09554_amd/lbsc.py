@@ -80,6 +80,8 @@ def library():
             "lbsc_step_count": (i64, [vp]),
             "lbsc_compute_moments": (ctypes.c_int, [vp, vp, vp, vp]),
             "lbsc_interface_diagnostics": (ctypes.c_int, [vp, dbl, dbl, P(Diag), P(dbl)]),
+            "lbsc_interface_diagnostics_static": (ctypes.c_int,
+                                                  [vp, dbl, dbl, P(Diag), P(dbl)]),
             "lbsc_get_state": (ctypes.c_int, [vp, vp, sz, P(i64)]),
             "lbsc_set_state": (ctypes.c_int, [vp, vp, sz, i64]),
             "lbsc_set_tuning": (ctypes.c_int, [vp, P(Tuning)]),
