@@ -126,10 +126,18 @@ def test_adjoint_matches_central_differences(prec, tol):
         fd["a%d" % (m + 1)] = (L(am=amps + e) - L(am=amps - e)) / (2 * h)
         ad["a%d" % (m + 1)] = float(a.grad[m])
     for k in fd:
-        print("%s %s: adjoint %.8e  fd %.8e" % (prec, k, ad[k], fd[k]), flush=True)
+        print("%s %s: adjoint %.8e  fd %.8e  rel err %.2e"
+              % (prec, k, ad[k], fd[k], abs(ad[k] - fd[k]) / abs(fd[k])), flush=True)
+    # Each component within tol of itself, except a component below 1e-3 of
+    # the largest: dL/ds_ghost here is 7e-7 against 0.85 for dL/da1.  Central
+    # differences of the float64 loss resolve it only to about 1e-11, and the
+    # float32 run's own rounding moves it by about 2e-8 (3 % of itself, 3e-8 of
+    # the gradient's scale), so such a component is held to tol times 1e-3 of
+    # the largest component instead.
     scale = max(abs(v) for v in fd.values())
     for k in fd:
-        assert abs(ad[k] - fd[k]) <= tol * max(abs(fd[k]), 1e-3 * scale), k
+        bound = tol * abs(fd[k]) if abs(fd[k]) >= 1e-3 * scale else tol * 1e-3 * scale
+        assert abs(ad[k] - fd[k]) <= bound, k
 
 
 def test_config5_full_size_adjoint_against_fd():
@@ -166,13 +174,16 @@ def test_config5_full_size_adjoint_against_fd():
         e[m] = h
         fd["a%d" % (m + 1)] = (L(am=amps + e) - L(am=amps - e)) / (2 * h)
     print("fd", fd, flush=True)
-    scale = max(abs(v) for v in fd.values())
     for k in fd:
+        e64 = abs(res["f64"][k] - fd[k]) / abs(fd[k])
+        e32 = abs(res["f32"][k] - fd[k]) / abs(fd[k])
+        print("%s: fd %.9e, f64 rel err %.2e, f32 rel err %.2e" % (k, fd[k], e64, e32), flush=True)
         # float64 adjoint: exact gradient of the float64 run (FD truncation
-        # error ~1e-8); float32 adjoint: gradient of the float32 run, which
-        # differs from the float64 run by its rounding (observed <= 1.1e-4).
-        assert abs(res["f64"][k] - fd[k]) <= 1e-6 * max(abs(fd[k]), 1e-3 * scale), ("f64", k)
-        assert abs(res["f32"][k] - fd[k]) <= 5e-4 * max(abs(fd[k]), 1e-3 * scale), ("f32", k)
+        # error ~1e-8); float32 storage: gradient of the float32 run (adjoint
+        # arithmetic in float64), which differs from the float64 run by its
+        # rounding.  Both relative to each component itself.
+        assert e64 <= 1e-6, ("f64", k, e64)
+        assert e32 <= 1e-4, ("f32", k, e32)
 
 
 def test_parameter_gradients_follow_their_inputs():
