@@ -265,7 +265,10 @@ void chunk_and_order(const lbsc_params* p, int32_t n, lbsc_tuning* t) {
   const long long columns = tile_columns(p, n, t->threads);
   const bool one_wave = t->threads == 1024 && n == 1;
   const long long groups = one_wave ? 256 : 512;
-  const long long zmax = one_wave ? 256 : 64;
+  // Batches: chunks of at most 8 planes (the 64-ligament sweep: 13.87 ms per
+  // step against 14.24 with 64-plane chunks, about 50 000 short-lived groups
+  // whose tail wave is a small fraction of the step).
+  const long long zmax = one_wave ? 256 : (n > 1 ? 8 : 64);
   long long zc = (columns + groups - 1) / groups;
   if (zc < 1) zc = 1;
   if (zc > zmax) zc = zmax;
@@ -274,7 +277,13 @@ void chunk_and_order(const lbsc_params* p, int32_t n, lbsc_tuning* t) {
   // plain dispatch order beats XCD-local tile ranges (measured 14.15 against
   // 13.87 GLUPS on 256 x 256 x 1024 MRT, eight waves); within one wave the
   // XCD-local ranges win (32 x 32 x 64: 7.2 against 5.9 GLUPS).
-  t->xcd_remap = (p[0].precision == LBSC_F64 && (columns + zc - 1) / zc > 512) ? 0 : 1;
+  // Batches run in plain dispatch order as well: consecutive entries of the
+  // tile table are neighbouring tiles of one member, so plain order keeps
+  // the groups in flight on one contiguous stretch of memory; XCD-local
+  // ranges cut the L2-missing halo reads (fetch 1.41 -> 1.11 x the
+  // algorithmic reads, the rest served by the memory-side cache) but spread
+  // the groups over eight stretches and run slower (14.47 against 14.27 ms).
+  t->xcd_remap = ((p[0].precision == LBSC_F64 && (columns + zc - 1) / zc > 512) || n > 1) ? 0 : 1;
 }
 
 lbsc_tuning default_tuning(const lbsc_params* p, int32_t n) {

@@ -328,11 +328,13 @@ __device__ inline R pull_sum(const T* __restrict__ lat, long long ps, const Nbr&
 }
 
 __device__ inline int remap_xcd(int b, int nb) {
-  // Work-groups are dispatched round-robin over the 8 XCDs.  Give each XCD a
-  // contiguous range of logical tiles so that tiles sharing halo rows share
-  // an L2.
-  if ((nb & 7) != 0) return b;
-  return (b & 7) * (nb >> 3) + (b >> 3);
+  // Work-groups are dispatched round-robin over the 8 XCDs: group b runs on
+  // XCD k = b mod 8 as that XCD's j = b div 8-th group.  Give each XCD a
+  // contiguous range of logical tiles, so that tiles sharing halo rows share
+  // an L2.  With nb = 8 q + r, XCD k holds q + [k < r] groups and its range
+  // starts at k q + min(k, r); the ranges tile [0, nb) exactly.
+  const int k = b & 7, j = b >> 3, q = nb >> 3, r = nb & 7;
+  return k * q + min(k, r) + j;
 }
 
 // psi at a node and its 18 neighbours: c; the axis neighbours x+ x- y+ y-
