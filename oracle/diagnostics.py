@@ -12,13 +12,19 @@
                  ties broken towards the smallest z.  It needs no axis
                  position and is piecewise differentiable.
 * velocity magnitude v* = |u^b| / (R0 / t_cap)                    (Sec. 4, Fig. 6)
+* break-up         the paper compares ligaments up to the pinch-off but
+                   states no criterion for it (Sec. 4, Fig. 2b).  Reading
+                   taken here: the column is cut once some z-slice holds no
+                   node denser than the mid density (rho_l + rho_v) / 2.
 
 Pins (tests/test_oracle_diagnostics.py): the liquid area of a sharp disc
 slice is its lattice-node count and its equivalent radius is the disc radius
 to O(1/R) (Gauss circle count); a tanh wall of width W adds pi^3 W^2 / 48 to
 the area (closed form); densities above rho_l count 1, below rho_v 0, the mid
 density 1/2; equal minima go to the smallest z; a state at rest has zero
-momentum; v* of a uniform flow is |u| t_cap / R0.  The pressure is not pinned
+momentum; v* of a uniform flow is |u| t_cap / R0; the neck is cut when one
+slice lies wholly at or below the mid density and not while a single node of
+every slice is above it.  The pressure is not pinned
 by restating Eq. EOS_SC: the EoS is pinned through the flat-interface
 coexistence densities and the Laplace law (tests/test_oracle_physics.py).
 """
@@ -64,6 +70,12 @@ def minimum_radius(rho, rho_v, rho_l):
     rmin = float(r.min())
     z = int(torch.nonzero(r == r.min())[0, 0])
     return rmin, z
+
+
+def neck_is_cut(rho, rho_v, rho_l):
+    """True once some z-slice of rho [nz, ny, nx] has no node above (rho_l + rho_v)/2."""
+    slice_max = rho.amax(dim=(-2, -1))
+    return bool((slice_max <= 0.5 * (rho_l + rho_v)).any())
 
 
 def interface_diagnostics(f, p, rho_v, rho_l):

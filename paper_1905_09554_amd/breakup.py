@@ -137,6 +137,17 @@ def break_time(R0, operator, eps=0.1, every=25, max_tcap=16.0, precision="f32", 
     state that turns non-finite ends the continuation and is reported as
     info["diverged_after_tcap"]."""
     rho0, info = lbm_inputs.paper_ligament(R0, operator, eps)
+    return run_to_breakup(rho0, info, operator, every=every, max_tcap=max_tcap,
+                          precision=precision, progress=progress, record=record,
+                          after_tcap=after_tcap)
+
+
+def run_to_breakup(rho0, info, operator, every=25, max_tcap=16.0, precision="f32",
+                   progress=False, record=None, after_tcap=0.0):
+    """The run of break_time from any initial density: info holds the box
+    (nx, ny, nz), G, tau, rho_l, rho_v, t_cap and R0 (and eps for the
+    progress lines).  Same return values."""
+    R0, eps = info["R0"], info.get("eps", float("nan"))
     sim = lbsc.Simulation(rho0, params_for(info, operator, precision))
     rec = Recorder(info) if record is True else (record or None)
     rho_mid = 0.5 * (info["rho_l"] + info["rho_v"])

@@ -154,3 +154,18 @@ def test_velocity_magnitude_star_of_a_uniform_flow():
     R0, t_cap = 14.0, 347.0
     v = diagnostics.velocity_magnitude_star(f, lbm.Params(G=-5.3, tau=0.7), R0, t_cap)
     assert float((v - 0.05 * t_cap / R0).abs().max()) < 1e-13
+
+
+def test_neck_is_cut_once_one_slice_is_wholly_vapour():
+    nz, n = 10, 16
+    rv, rl = 0.125, 1.875
+    mid = 0.5 * (rv + rl)
+    rho = torch.from_numpy(lbm_inputs.density_from_radius(n, n, [5.0] * nz, rv, rl))
+    assert not diagnostics.neck_is_cut(rho, rv, rl)
+    cut = rho.clone()
+    cut[7] = rv                      # slice 7 all vapour
+    assert diagnostics.neck_is_cut(cut, rv, rl)
+    cut[7, 3, 4] = mid + 1e-9        # one node above the mid density keeps it whole
+    assert not diagnostics.neck_is_cut(cut, rv, rl)
+    cut[7, 3, 4] = mid               # at the mid density it is cut
+    assert diagnostics.neck_is_cut(cut, rv, rl)
