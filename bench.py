@@ -325,13 +325,28 @@ def cpu_model():
     return None
 
 
+def host_threads():
+    """Threads the oracle may use: the CPUs this process may run on, within
+    the OpenMP thread limit the host sets (the GPU machine grants each GPU a
+    share of its cores)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(1, n)
+
+
 def cpu_baseline(rho0, info, nz_sample=16, steps=40):
     """The float64 oracle on the host: the first nz_sample planes of the same
-    input as a periodic slab, `steps` steps, reported in MLUPS."""
+    input as a periodic slab, `steps` steps, reported in MLUPS; also on one
+    thread, for 4 steps."""
     import torch
     from oracle import lbm
 
-    torch.set_num_threads(min(16, os.cpu_count() or 1))
+    torch.set_num_threads(host_threads())
     sample = rho0[:nz_sample].copy()
     p = lbm.Params(G=info["G"], tau=info["tau"], collision=info["collision"])
     f = lbm.init_rest(torch.from_numpy(sample))
@@ -342,10 +357,20 @@ def cpu_baseline(rho0, info, nz_sample=16, steps=40):
     dt = time.perf_counter() - t0
     out = {"value": round(sample.size * steps / dt / 1e6, 3), "unit": "MLUPS",
            "cores": torch.get_num_threads(), "kind": "oracle", "cpu_model": cpu_model(),
-           "sample": "%dx%dx%d periodic slab (first %d planes of the benchmark input), "
-                     "%s float64, %d steps, %.1f s" % (sample.shape[2], sample.shape[1],
-                                                       nz_sample, nz_sample, info["collision"],
-                                                       steps, dt)}
+           "host_cpus": os.cpu_count(), "sample": "%dx%dx%d periodic slab (first %d planes of "
+           "the benchmark input), %s float64, %d steps, %.1f s" % (
+               sample.shape[2], sample.shape[1], nz_sample, nz_sample, info["collision"], steps,
+               dt)}
+    nthreads = torch.get_num_threads()
+    torch.set_num_threads(1)
+    f = lbm.step(lbm.init_rest(torch.from_numpy(sample)), p)
+    t0 = time.perf_counter()
+    for _ in range(4):
+        f = lbm.step(f, p)
+    dt1 = time.perf_counter() - t0
+    torch.set_num_threads(nthreads)
+    out["one_thread"] = {"value": round(sample.size * 4 / dt1 / 1e6, 3), "unit": "MLUPS",
+                         "steps": 4, "seconds": round(dt1, 2)}
     # A 20-step window of the 128 x 128 x 512 ligament (first 64 planes), BGK.
     import lbm_inputs
     rho2, info2 = lbm_inputs.workload_density("ligament_128x128x512")
