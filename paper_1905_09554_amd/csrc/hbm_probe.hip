@@ -2,16 +2,33 @@
 // It is the denominator next to the 8 TB/s datasheet peak when the step's
 // achieved bandwidth is compared.  Prints one line per kernel and launch shape.
 //
-//   paper_1905_09554_amd/hbm_probe
+//   paper_1905_09554_amd/hbm_probe [gridstride|onepass|stream|lds|pull|all]
 //
-// Kernels: float4 copy (read + write; also with non-temporal stores, with
-// non-temporal loads and stores, and with four loads in flight per thread),
-// float copy, float4 read-only (sum), float4 write-only (fill), and a
-// 19-array stream (19 reads + 19 writes of float per node, the step's memory
-// pattern without the stencil; also with non-temporal stores).
+// Families (every kernel moves a known number of bytes, timed over 10 launches
+// after a warm-up with HIP events):
+//  gridstride  float4 copy with a grid-stride loop (plain, non-temporal stores,
+//              non-temporal loads and stores, four loads in flight per
+//              thread), float copy, float4 read-only and write-only, for
+//              256-, 512- and 1024-thread work-groups;
+//  onepass     one pass over the buffer, no loop: work-group b copies its own
+//              contiguous block of T * K float4, each thread K of them (all K
+//              loads issued before the first store); also read-only and
+//              write-only in the same shape;
+//  stream      the step's memory pattern without its stencil: 19 arrays of
+//              floats read and 19 written per node, one node per thread (one
+//              pass), or a work-group marching a contiguous range of nodes with
+//              the next chunk's 19 loads in flight during the current chunk's
+//              stores (as the step carries the next plane in registers);
+//  lds         float4 copy staged through LDS with gfx950's direct
+//              global-to-LDS loads (global_load_lds_dwordx4): K float4 per
+//              lane land in LDS without passing through registers, then each
+//              lane reads its values back and stores them;
+//  pull        the step's own pattern without the stencil (see pull_march),
+//              in the 19-array layout and in blocks of 64 nodes.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstring>
 
 #define CK(x)                                                                   \
   do {                                                                          \
@@ -22,6 +39,10 @@
     }                                                                           \
   } while (0)
 
+// The non-temporal builtins take clang's own vector types.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------- grid-stride
 __global__ void copy4(const float4* __restrict__ a, float4* __restrict__ b, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)
@@ -46,10 +67,6 @@ __global__ void write4(float4* __restrict__ b, size_t n) {
        i += (size_t)gridDim.x * blockDim.x)
     b[i] = make_float4(1.f, 2.f, 3.f, 4.f);
 }
-// The non-temporal builtins take clang's own vector types.
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-// float4 copy with non-temporal stores, and with non-temporal loads too.
 __global__ void copy4_nt(const v4f* __restrict__ a, v4f* __restrict__ b, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)
@@ -73,31 +90,153 @@ __global__ void copy4_u4(const v4f* __restrict__ a, v4f* __restrict__ b, size_t 
   }
   for (; i < n; i += stride) __builtin_nontemporal_store(a[i], &b[i]);
 }
-// The 19-array stream with non-temporal stores (as the step writes).
-__global__ void stream19_nt(const float* __restrict__ a, float* __restrict__ b, size_t n,
-                            size_t ps) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x) {
-    float v[19];
+
+// ---------------------------------------------------------------- one pass
+// Work-group b owns float4 elements [b T K, (b + 1) T K); thread t handles
+// b T K + k T + t for k < K.  n must be a multiple of T K (checked on the
+// host).  NT: non-temporal stores.
+template <int K, bool NT>
+__global__ void copy_onepass(const v4f* __restrict__ a, v4f* __restrict__ b) {
+  const size_t base = (size_t)blockIdx.x * blockDim.x * K + threadIdx.x;
+  v4f v[K];
 #pragma unroll
-    for (int q = 0; q < 19; ++q) v[q] = a[q * ps + i];
+  for (int k = 0; k < K; ++k) v[k] = a[base + (size_t)k * blockDim.x];
 #pragma unroll
-    for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(v[q] * 1.0001f, &b[q * ps + i]);
+  for (int k = 0; k < K; ++k) {
+    if (NT)
+      __builtin_nontemporal_store(v[k], &b[base + (size_t)k * blockDim.x]);
+    else
+      b[base + (size_t)k * blockDim.x] = v[k];
   }
 }
-__global__ void stream19(const float* __restrict__ a, float* __restrict__ b, size_t n,
-                         size_t ps) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x) {
-    float v[19];
+template <int K>
+__global__ void read_onepass(const v4f* __restrict__ a, float* __restrict__ out) {
+  const size_t base = (size_t)blockIdx.x * blockDim.x * K + threadIdx.x;
+  v4f v[K];
 #pragma unroll
-    for (int q = 0; q < 19; ++q) v[q] = a[q * ps + i];
+  for (int k = 0; k < K; ++k) v[k] = a[base + (size_t)k * blockDim.x];
+  float s = 0;
 #pragma unroll
-    for (int q = 0; q < 19; ++q) b[q * ps + i] = v[q] * 1.0001f;
+  for (int k = 0; k < K; ++k) s += v[k].x + v[k].y + v[k].z + v[k].w;
+  if (s == 1234.5f) out[0] = s;
+}
+template <int K>
+__global__ void write_onepass(v4f* __restrict__ b) {
+  const size_t base = (size_t)blockIdx.x * blockDim.x * K + threadIdx.x;
+  const v4f one = {1.f, 2.f, 3.f, 4.f};
+#pragma unroll
+  for (int k = 0; k < K; ++k) __builtin_nontemporal_store(one, &b[base + (size_t)k * blockDim.x]);
+}
+
+// ------------------------------------------------------------ 19-array stream
+// One node per thread, one pass: n must be a multiple of the work-group size.
+__global__ void stream19_onepass(const float* __restrict__ a, float* __restrict__ b, size_t ps) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  float v[19];
+#pragma unroll
+  for (int q = 0; q < 19; ++q) v[q] = a[q * ps + i];
+#pragma unroll
+  for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(v[q] * 1.0001f, &b[q * ps + i]);
+}
+// Work-group b marches `chunks` consecutive chunks of blockDim.x nodes; the
+// loads of chunk c + 1 are issued before the stores of chunk c.
+__global__ void stream19_march(const float* __restrict__ a, float* __restrict__ b, size_t ps,
+                               int chunks) {
+  const size_t first = (size_t)blockIdx.x * chunks * blockDim.x + threadIdx.x;
+  float cur[19], nxt[19];
+#pragma unroll
+  for (int q = 0; q < 19; ++q) cur[q] = a[q * ps + first];
+  for (int c = 0; c < chunks; ++c) {
+    const size_t i = first + (size_t)c * blockDim.x;
+    const size_t j = c + 1 < chunks ? i + blockDim.x : i;
+#pragma unroll
+    for (int q = 0; q < 19; ++q) nxt[q] = a[q * ps + j];
+#pragma unroll
+    for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(cur[q] * 1.0001f, &b[q * ps + i]);
+#pragma unroll
+    for (int q = 0; q < 19; ++q) cur[q] = nxt[q];
   }
 }
 
-int main() {
+// ------------------------------------------------- direct global-to-LDS copy
+// Each wave loads K float4 per lane straight into its own LDS slice (the LDS
+// address of a global_load_lds is the wave-uniform base plus 16 B per lane),
+// waits, reads them back and stores them.  Work-group b owns T K float4 as in
+// copy_onepass.
+template <int K>
+__global__ void copy_lds(const v4f* __restrict__ a, v4f* __restrict__ b) {
+  extern __shared__ __attribute__((aligned(16))) v4f stage[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const size_t base = (size_t)blockIdx.x * blockDim.x * K + threadIdx.x;
+  v4f* mine = stage + (size_t)wave * 64 * K;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    __builtin_amdgcn_global_load_lds((const void*)&a[base + (size_t)k * blockDim.x],
+                                     (__attribute__((address_space(3))) void*)(mine + k * 64), 16,
+                                     0, 0);
+  __builtin_amdgcn_s_waitcnt(0);  // vmcnt(0): every load of this wave has landed
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    __builtin_nontemporal_store(mine[k * 64 + lane], &b[base + (size_t)k * blockDim.x]);
+}
+
+// ------------------------------------------------------------ pull pattern
+// The step's HBM pattern without its stencil, collision or halo: a box of
+// nx x ny x nz nodes (nx = 256 here), work-group of 1024 threads owning a
+// tile of 4 whole rows and marching zc planes; per plane each thread pulls
+// the 19 populations of its node from the neighbours x - c_a (periodic), keeps
+// them in registers for one plane, and stores the previous plane's 19 values
+// at its own node (non-temporal).  Two population layouts:
+//   soa    population a of node i at a * ps + i (19 arrays);
+//   blkB   blocks of B consecutive nodes, the block's 19 populations
+//          contiguous: ((i / B) * 19 + a) * B + i mod B (B = 64 ... 4096).
+__device__ constexpr int PCX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+__device__ constexpr int PCY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+__device__ constexpr int PCZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+// B = 0: the 19-array layout; B > 0: blocks of B consecutive nodes.
+template <int B>
+__device__ inline size_t paddr(int a, unsigned i, size_t ps) {
+  if (B > 0) return ((size_t)(i / B) * 19 + a) * B + (i % B);
+  return (size_t)a * ps + i;
+}
+
+template <int BLK>
+__global__ void __launch_bounds__(1024)
+pull_march(const float* __restrict__ src, float* __restrict__ dst, int nx, int ny, int nz,
+           int zc, size_t ps) {
+  const int tiles_y = ny / 4;
+  const int ty = blockIdx.x % tiles_y, chunk = blockIdx.x / tiles_y;
+  const int x = threadIdx.x % nx, y = ty * 4 + threadIdx.x / nx;
+  const int z0 = chunk * zc, z1 = z0 + zc;
+  const unsigned plane = (unsigned)nx * ny;
+  const int xo[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
+  const int yo[3] = {(y == 0 ? ny - 1 : y - 1) * nx, y * nx, (y == ny - 1 ? 0 : y + 1) * nx};
+  float cur[19], nxt[19];
+  auto load = [&](int z, float(&v)[19]) {
+    const unsigned zo[3] = {(unsigned)(z == 0 ? nz - 1 : z - 1) * plane, (unsigned)z * plane,
+                            (unsigned)(z == nz - 1 ? 0 : z + 1) * plane};
+#pragma unroll
+    for (int a = 0; a < 19; ++a) {
+      const unsigned i = zo[1 - PCZ[a]] + yo[1 - PCY[a]] + xo[1 - PCX[a]];
+      v[a] = src[paddr<BLK>(a, i, ps)];
+    }
+  };
+  load(z0, cur);
+  for (int z = z0; z < z1; ++z) {
+    load(z + 1 < nz ? z + 1 : 0, nxt);
+    const unsigned i = (unsigned)z * plane + yo[1] + x;
+#pragma unroll
+    for (int a = 0; a < 19; ++a) __builtin_nontemporal_store(cur[a] * 1.0001f, &dst[paddr<BLK>(a, i, ps)]);
+#pragma unroll
+    for (int a = 0; a < 19; ++a) cur[a] = nxt[a];
+  }
+}
+
+int main(int argc, char** argv) {
+  const char* fam = argc > 1 ? argv[1] : "all";
+  auto want = [&](const char* f) { return !std::strcmp(fam, "all") || !std::strcmp(fam, f); };
   const size_t bytes = (size_t)4 << 30;  // two 4 GiB buffers
   float *a, *b, *o;
   CK(hipMalloc(&a, bytes));
@@ -111,8 +250,9 @@ int main() {
   const size_t n4 = bytes / 16, n1 = bytes / 4;
   // 19 arrays of n floats with stride ps: 19 * ps * 4 B = 2.55 GB < 4 GiB.
   const size_t n19 = 33554432, ps19 = n19 + 1088;
-  auto run = [&](const char* name, int grid, double traffic, auto launch) -> int {
+  auto run = [&](const char* name, int threads, int grid, double traffic, auto launch) -> int {
     launch();
+    CK(hipGetLastError());
     CK(hipDeviceSynchronize());
     CK(hipEventRecord(e0));
     for (int r = 0; r < 10; ++r) launch();
@@ -121,30 +261,115 @@ int main() {
     float ms;
     CK(hipEventElapsedTime(&ms, e0, e1));
     ms /= 10;
-    std::printf("%-11s grid %6d  %8.3f ms  %8.1f GB/s\n", name, grid, ms, traffic / ms / 1e6);
+    std::printf("%-16s threads %5d grid %8d  %8.3f ms  %8.1f GB/s\n", name, threads, grid, ms,
+                traffic / ms / 1e6);
     std::fflush(stdout);
     return 0;
   };
-  for (int grid : {1024, 2048, 4096, 16384, 65536}) {
-    if (run("copy4", grid, 2.0 * bytes, [&] { copy4<<<grid, 256>>>((float4*)a, (float4*)b, n4); }))
-      return 1;
-    if (run("copy4_nt", grid, 2.0 * bytes,
-            [&] { copy4_nt<<<grid, 256>>>((v4f*)a, (v4f*)b, n4); }))
-      return 1;
-    if (run("copy4_ntld", grid, 2.0 * bytes,
-            [&] { copy4_ntld<<<grid, 256>>>((v4f*)a, (v4f*)b, n4); }))
-      return 1;
-    if (run("copy4_u4", grid, 2.0 * bytes,
-            [&] { copy4_u4<<<grid, 256>>>((v4f*)a, (v4f*)b, n4); }))
-      return 1;
-    if (run("stream19nt", grid, 2.0 * 19 * n19 * 4,
-            [&] { stream19_nt<<<grid, 256>>>(a, b, n19, ps19); }))
-      return 1;
-    if (run("copy1", grid, 2.0 * bytes, [&] { copy1<<<grid, 256>>>(a, b, n1); })) return 1;
-    if (run("read4", grid, 1.0 * bytes, [&] { read4<<<grid, 256>>>((float4*)a, o, n4); })) return 1;
-    if (run("write4", grid, 1.0 * bytes, [&] { write4<<<grid, 256>>>((float4*)b, n4); })) return 1;
-    if (run("stream19", grid, 2.0 * 19 * n19 * 4, [&] { stream19<<<grid, 256>>>(a, b, n19, ps19); }))
-      return 1;
+  if (want("gridstride")) {
+    for (int t : {256, 512, 1024}) {
+      for (int grid : {1024, 2048, 4096, 16384, 65536}) {
+        if (run("copy4", t, grid, 2.0 * bytes,
+                [&] { copy4<<<grid, t>>>((float4*)a, (float4*)b, n4); }))
+          return 1;
+        if (run("copy4_nt", t, grid, 2.0 * bytes,
+                [&] { copy4_nt<<<grid, t>>>((v4f*)a, (v4f*)b, n4); }))
+          return 1;
+        if (run("copy4_ntld", t, grid, 2.0 * bytes,
+                [&] { copy4_ntld<<<grid, t>>>((v4f*)a, (v4f*)b, n4); }))
+          return 1;
+        if (run("copy4_u4", t, grid, 2.0 * bytes,
+                [&] { copy4_u4<<<grid, t>>>((v4f*)a, (v4f*)b, n4); }))
+          return 1;
+        if (run("copy1", t, grid, 2.0 * bytes, [&] { copy1<<<grid, t>>>(a, b, n1); })) return 1;
+        if (run("read4", t, grid, 1.0 * bytes,
+                [&] { read4<<<grid, t>>>((float4*)a, o, n4); }))
+          return 1;
+        if (run("write4", t, grid, 1.0 * bytes, [&] { write4<<<grid, t>>>((float4*)b, n4); }))
+          return 1;
+      }
+    }
+  }
+  if (want("onepass")) {
+    // n4 = 2^28 is a multiple of every T K below.
+    for (int t : {256, 512, 1024}) {
+      auto one = [&](auto kc) -> int {
+        constexpr int K = decltype(kc)::value;
+        const int grid = (int)(n4 / ((size_t)t * K));
+        char name[32];
+        std::snprintf(name, sizeof(name), "copy_1p_k%d", K);
+        if (run(name, t, grid, 2.0 * bytes,
+                [&] { copy_onepass<K, false><<<grid, t>>>((v4f*)a, (v4f*)b); }))
+          return 1;
+        std::snprintf(name, sizeof(name), "copy_1p_nt_k%d", K);
+        if (run(name, t, grid, 2.0 * bytes,
+                [&] { copy_onepass<K, true><<<grid, t>>>((v4f*)a, (v4f*)b); }))
+          return 1;
+        std::snprintf(name, sizeof(name), "read_1p_k%d", K);
+        if (run(name, t, grid, 1.0 * bytes, [&] { read_onepass<K><<<grid, t>>>((v4f*)a, o); }))
+          return 1;
+        std::snprintf(name, sizeof(name), "write_1p_k%d", K);
+        if (run(name, t, grid, 1.0 * bytes, [&] { write_onepass<K><<<grid, t>>>((v4f*)b); }))
+          return 1;
+        return 0;
+      };
+      if (one(std::integral_constant<int, 1>{}) || one(std::integral_constant<int, 2>{}) ||
+          one(std::integral_constant<int, 4>{}) || one(std::integral_constant<int, 8>{}))
+        return 1;
+    }
+  }
+  if (want("stream")) {
+    // n19 = 2^25 nodes: a multiple of every work-group size and chunk count.
+    for (int t : {256, 512, 1024}) {
+      const int grid = (int)(n19 / t);
+      if (run("stream19_1p", t, grid, 2.0 * 19 * n19 * 4,
+              [&] { stream19_onepass<<<grid, t>>>(a, b, ps19); }))
+        return 1;
+      for (int chunks : {4, 16, 64, 256}) {
+        const int g = (int)(n19 / ((size_t)t * chunks));
+        char name[32];
+        std::snprintf(name, sizeof(name), "stream19_m%d", chunks);
+        if (run(name, t, g, 2.0 * 19 * n19 * 4,
+                [&] { stream19_march<<<g, t>>>(a, b, ps19, chunks); }))
+          return 1;
+      }
+    }
+  }
+  if (want("lds")) {
+    for (int t : {256, 512, 1024}) {
+      auto one = [&](auto kc) -> int {
+        constexpr int K = decltype(kc)::value;
+        const int grid = (int)(n4 / ((size_t)t * K));
+        const size_t lds = (size_t)t * K * 16;
+        if (lds > 64 * 1024) return 0;  // within the default dynamic LDS limit
+        char name[32];
+        std::snprintf(name, sizeof(name), "copy_lds_k%d", K);
+        return run(name, t, grid, 2.0 * bytes,
+                   [&] { copy_lds<K><<<grid, t, lds>>>((v4f*)a, (v4f*)b); });
+      };
+      if (one(std::integral_constant<int, 1>{}) || one(std::integral_constant<int, 2>{}) ||
+          one(std::integral_constant<int, 4>{}) || one(std::integral_constant<int, 8>{}))
+        return 1;
+    }
+  }
+  if (want("pull")) {
+    // 256 x 256 x 512 box: 33.5 M nodes, 19 x 4 B x n = 2.55 GB per lattice.
+    const int nx = 256, ny = 256, nz = 512;
+    const size_t n = (size_t)nx * ny * nz, ps = n + 1088;
+    for (int zc : {128, 8}) {
+      const int grid = (ny / 4) * (nz / zc);
+      auto one = [&](auto bc) -> int {
+        constexpr int B = decltype(bc)::value;
+        char name[32];
+        std::snprintf(name, sizeof(name), "pull_blk%d_z%d", B, zc);
+        return run(name, 1024, grid, 2.0 * 19 * n * 4,
+                   [&] { pull_march<B><<<grid, 1024>>>(a, b, nx, ny, nz, zc, ps); });
+      };
+      if (one(std::integral_constant<int, 0>{}) || one(std::integral_constant<int, 64>{}) ||
+          one(std::integral_constant<int, 256>{}) || one(std::integral_constant<int, 1024>{}) ||
+          one(std::integral_constant<int, 4096>{}))
+        return 1;
+    }
   }
   CK(hipFree(a));
   CK(hipFree(b));
