@@ -92,7 +92,9 @@ typedef struct lbsc_diag {
  * than half the group; 2 otherwise) and 2 nx <= threads, else the widest
  * multiple of 64 whose tile and halo ring (2 (block_x + 2) + 2 block_y nodes)
  * fit the work-group.  lbsc_default_tuning gives the whole default on the
- * host.  Changing pop_pad re-lays the state out in place (same values). */
+ * host.  The populations are stored in blocks of 1024 consecutive nodes,
+ * each block holding its 19 populations one after the other; pop_pad, the
+ * padding of a layout with one array per population, is then ignored. */
 typedef struct lbsc_tuning {
   int32_t threads;     /* work-group size of the fused step: 256, 512, 1024   */
   int32_t z_chunk;     /* planes marched per work-group (>= 1)                */
@@ -100,7 +102,8 @@ typedef struct lbsc_tuning {
                           < 0: the default (1, except 0 for float64 boxes
                           of more than one wave of work-groups)             */
   int32_t block_y;     /* rows per tile; 0 = as many as the work-group holds  */
-  int32_t pop_pad;     /* extra elements between population arrays, <= 65536 */
+  int32_t pop_pad;     /* padding between population arrays, <= 65536 (only
+                          for one array per population; see above)        */
   int32_t nodes_per_thread; /* interior nodes each thread carries: 1 or 2      */
   int32_t persistent;  /* 1: all steps of one lbsc_step call in one cooperative
                           launch with grid barriers; 0: one launch per step   */
@@ -112,11 +115,10 @@ typedef struct lbsc_tuning {
 } lbsc_tuning;
 
 /* Bytes of device memory a context with these parameters needs: two
- * population lattices of 19 arrays of nx * ny * nz values in the storage
- * precision (each array padded by up to 65536 elements so the arrays do not
- * share HBM channels), plus a reduction area and the psi field of the
- * two-kernel form of the step (nx * ny * nz values).  Returns 0 for invalid
- * parameters. */
+ * population lattices of 19 nx * ny * nz values in the storage precision
+ * (with room for 65536 padding elements per population), plus a reduction
+ * area and the psi field of the two-kernel form of the step (nx * ny * nz
+ * values).  Returns 0 for invalid parameters. */
 size_t lbsc_state_bytes(const lbsc_params* p);
 
 /* Creates a context and sets the initial state f_a(x) = w_a rho0(x) (zero

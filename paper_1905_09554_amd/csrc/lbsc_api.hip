@@ -128,6 +128,17 @@ double* scratch_of(int dev) {
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 size_t elem_size(const lbsc_params& p) { return p.precision == LBSC_F64 ? 8 : 4; }
 long long nodes(const lbsc_params& p) { return (long long)p.nx * p.ny * p.nz; }
+// Block length of the population layout of the storage type (0: one array
+// per population, padded by the tuning's pop_pad).
+long long layout_block(const lbsc_params& p) {
+  return p.precision == LBSC_F64 ? lbsc::Layout<double>::kBlock : lbsc::Layout<float>::kBlock;
+}
+// Nodes a lattice holds room for: n rounded up to the layout's blocks, or
+// to 64 nodes plus the padding between population arrays.
+long long lattice_nodes(const lbsc_params& p, long long pad) {
+  const long long B = layout_block(p);
+  return B > 0 ? (nodes(p) + B - 1) / B * B : (nodes(p) + 63) / 64 * 64 + pad;
+}
 
 int fail(std::string* where, int code, const std::string& msg) {
   if (where) *where = msg;
@@ -224,7 +235,7 @@ lbsc::StepArgs make_args(const lbsc_params& p, const lbsc_tuning& t, long long p
   a.nz = p.nz;
   a.plane = p.nx * p.ny;
   a.n = nodes(p);
-  a.ps = (a.n + 63) / 64 * 64 + pad;
+  a.ps = lattice_nodes(p, pad);
   tile_shape(p.nx, p.ny, (long long)t.nodes_per_thread * t.threads, t.threads, t.block_x,
              t.block_y, elem_size(p), &a.bx, &a.by);
   a.ntiles_x = (p.nx + a.bx - 1) / a.bx;
@@ -323,8 +334,10 @@ lbsc_tuning default_tuning(const lbsc_params* p, int32_t n) {
   return t;
 }
 
+// Capacity of a lattice: room for every padding up to `pad` in either layout.
 size_t lattice_bytes(const lbsc_params& p, long long pad) {
-  return align_up((size_t)lbsc::Q * (size_t)((nodes(p) + 63) / 64 * 64 + pad) * elem_size(p));
+  const long long room = std::max(lattice_nodes(p, pad), (nodes(p) + 63) / 64 * 64 + pad);
+  return align_up((size_t)lbsc::Q * (size_t)room * elem_size(p));
 }
 
 // Sizes of the aux area (tile capacity: the finest tiling allowed, one row of
@@ -853,7 +866,7 @@ int lbsc_set_tuning(lbsc_ctx* c, const lbsc_tuning* t) {
   if (t->block_y && (long long)t->block_y * std::max(1, t->block_x) > cap)
     return fail(&c->err, LBSC_EINVAL, "block_x * block_y exceeds nodes_per_thread * threads");
   if (t->pop_pad > kMaxPad) return fail(&c->err, LBSC_EINVAL, "pop_pad exceeds 65536");
-  if (c->batch && t->pop_pad >= 0 && t->pop_pad != kDefaultPad)
+  if (c->batch && t->pop_pad >= 0 && t->pop_pad != kDefaultPad && layout_block(c->m[0].p) == 0)
     return fail(&c->err, LBSC_EINVAL, "a batch keeps the default population padding");
   if (t->persistent != 0 && t->persistent != 1)
     return fail(&c->err, LBSC_EINVAL, "persistent must be 0 or 1");

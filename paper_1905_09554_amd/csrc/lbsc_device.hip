@@ -7,11 +7,11 @@
 // SRT velocity shift of Eq. vel_shift; SRT (BGK) or MRT collision; equation of
 // state Eq. EOS_SC.
 //
-// Storage: structure of arrays, population a of node (x, y, z) at
-// lat[a * ps + (z * ny + y) * nx + x], with a population stride ps >= n that
-// is padded so the 19 streams do not fall on the same HBM channels.  A
-// lattice holds post-collision values
-// at their own node ("pull" layout): the post-streaming population of x is
+// Storage: node i = (z * ny + y) * nx + x; the nodes are cut into blocks of
+// consecutive nodes whose 19 populations are stored one after the other
+// (lat_index, lbsc_internal.h), so a work-group streams a few long runs of
+// memory rather than 19 arrays.  A lattice holds post-collision values at
+// their own node ("pull" layout): the post-streaming population of x is
 // f_a(x) = lat[a][x - c_a], so the step reads with +-1 offsets and writes
 // aligned.  In float32 storage the values are shifted, g_a = f_a - w_a rho_ref,
 // and every formula below is written for g (rho_ref = 0 gives plain f).
@@ -312,7 +312,7 @@ __device__ inline void pull(const T* __restrict__ lat, long long ps, const Nbr& 
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     const unsigned idx = b.zo[1 - CZ[a]] + b.yo[1 - CY[a]] + b.xo[1 - CX[a]];
-    f[a] = R(lat[(long long)a * ps + idx]);
+    f[a] = R(lat[lat_index<T>(a, idx, ps)]);
   }
 }
 
@@ -322,7 +322,7 @@ __device__ inline R pull_sum(const T* __restrict__ lat, long long ps, const Nbr&
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     const unsigned idx = b.zo[1 - CZ[a]] + b.yo[1 - CY[a]] + b.xo[1 - CX[a]];
-    s += R(lat[(long long)a * ps + idx]);
+    s += R(lat[lat_index<T>(a, idx, ps)]);
   }
   return s;
 }
@@ -546,7 +546,7 @@ __device__ inline void step_tile(const T* __restrict__ src, T* __restrict__ dst,
       // them from evicting the rows the neighbouring tiles still re-read.
 #pragma unroll
       for (int q = 0; q < Q; ++q)
-        __builtin_nontemporal_store(T(cur[k][q]), &dst[(long long)q * ps + idx]);
+        __builtin_nontemporal_store(T(cur[k][q]), &dst[lat_index<T>(q, idx, ps)]);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k)
@@ -629,7 +629,7 @@ k_step_psi(const T* __restrict__ src, const T* __restrict__ psi, T* __restrict__
     collide<R, COLL, FORC>(f, Fx, Fy, Fz, ph);
 #pragma unroll
     for (int qq = 0; qq < Q; ++qq)
-      __builtin_nontemporal_store(T(f[qq]), &dst[(long long)qq * a.ps + i]);
+      __builtin_nontemporal_store(T(f[qq]), &dst[lat_index<T>(qq, (unsigned)i, a.ps)]);
   }
 }
 
@@ -735,12 +735,13 @@ k_init(T* __restrict__ lat, const double* __restrict__ rho0, StepArgs a) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const unsigned src = nb.zo[1 + CZ[q]] + nb.yo[1 + CY[q]] + nb.xo[1 + CX[q]];
-      lat[(long long)q * a.ps + i] = T(weight<double>(q) * (rho0[src] - a.rho_ref));
+      lat[lat_index<T>(q, (unsigned)i, a.ps)] = T(weight<double>(q) * (rho0[src] - a.rho_ref));
     }
   }
 }
 
-// Post-streaming populations of every node into out[a][x] (state export).
+// Post-streaming populations of every node into the plain arrays
+// out[a * ps_out + x] (state export); ps_in is the lattice's own size.
 template <class T>
 __global__ void __launch_bounds__(256)
 k_gather(const T* __restrict__ lat, long long ps_in, T* __restrict__ out, long long ps_out,
@@ -755,12 +756,13 @@ k_gather(const T* __restrict__ lat, long long ps_in, T* __restrict__ out, long l
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const unsigned src = nb.zo[1 - CZ[q]] + nb.yo[1 - CY[q]] + nb.xo[1 - CX[q]];
-      out[(long long)q * ps_out + i] = lat[(long long)q * ps_in + src];
+      out[(long long)q * ps_out + i] = lat[lat_index<T>(q, src, ps_in)];
     }
   }
 }
 
-// Inverse of k_gather (state import): lat[a][y] = in[a][y + c_a].
+// Inverse of k_gather (state import) from plain arrays in[a * ps_in + x]:
+// lat[a][y] = in[a][y + c_a]; ps_out is the lattice's own size.
 template <class T>
 __global__ void __launch_bounds__(256)
 k_scatter(const T* __restrict__ in, long long ps_in, T* __restrict__ lat, long long ps_out,
@@ -775,7 +777,7 @@ k_scatter(const T* __restrict__ in, long long ps_in, T* __restrict__ lat, long l
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const unsigned src = nb.zo[1 + CZ[q]] + nb.yo[1 + CY[q]] + nb.xo[1 + CX[q]];
-      lat[(long long)q * ps_out + i] = in[(long long)q * ps_in + src];
+      lat[lat_index<T>(q, (unsigned)i, ps_out)] = in[(long long)q * ps_in + src];
     }
   }
 }
@@ -1024,7 +1026,7 @@ __global__ void __launch_bounds__(256) k_adj_collide(AdjArgs g) {
     static_for<Q>([&](auto bc) {
       constexpr int b = decltype(bc)::value;
       const unsigned idx = nb.zo[1 + CZ[b]] + nb.yo[1 + CY[b]] + nb.xo[1 + CX[b]];
-      gb[b] = R(pn[(long long)b * a.ps + idx]) + R(rn[idx]);
+      gb[b] = R(pn[lat_index<T>(b, idx, a.ps)]) + R(rn[idx]);
     });
     // Shan-Chen force at x from the density field of this step.
     R vx = R(0), vy = R(0), vz = R(0);
@@ -1217,7 +1219,7 @@ __global__ void __launch_bounds__(256) k_adj_collide(AdjArgs g) {
       if constexpr (CX[q] != 0) v += R(CX[q]) * jbx;
       if constexpr (CY[q] != 0) v += R(CY[q]) * jby;
       if constexpr (CZ[q] != 0) v += R(CZ[q]) * jbz;
-      po[(long long)q * a.ps + i] = T(v);
+      po[lat_index<T>(q, (unsigned)i, a.ps)] = T(v);
     });
     // For kernel B: the local half of dL/dpsi(x) and the field its
     // transposed stencil gathers.
@@ -1283,7 +1285,7 @@ __global__ void __launch_bounds__(256) k_adj_seed(AdjArgs g, const double* __res
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.n;
        i += (long long)gridDim.x * blockDim.x) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) po[(long long)q * a.ps + i] = T(0);
+    for (int q = 0; q < Q; ++q) po[lat_index<T>(q, (unsigned)i, a.ps)] = T(0);
     ro[i] = T(rhobar[i]);
   }
 }
@@ -1298,7 +1300,8 @@ __global__ void __launch_bounds__(256) k_adj_final(AdjArgs g, double* __restrict
        i += (long long)gridDim.x * blockDim.x) {
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) s += weight<double>(q) * double(pn[(long long)q * a.ps + i]);
+    for (int q = 0; q < Q; ++q)
+      s += weight<double>(q) * double(pn[lat_index<T>(q, (unsigned)i, a.ps)]);
     rho0bar[i] = s + double(rn[i]);
   }
 }
