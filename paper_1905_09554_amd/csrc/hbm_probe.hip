@@ -2,7 +2,7 @@
 // It is the denominator next to the 8 TB/s datasheet peak when the step's
 // achieved bandwidth is compared.  Prints one line per kernel and launch shape.
 //
-//   paper_1905_09554_amd/hbm_probe [gridstride|onepass|stream|lds|pull|all]
+//   paper_1905_09554_amd/hbm_probe [gridstride|onepass|stream|lds|pull|lds19|all]
 //
 // Families (every kernel moves a known number of bytes, timed over 10 launches
 // after a warm-up with HIP events):
@@ -24,7 +24,9 @@
 //              lane land in LDS without passing through registers, then each
 //              lane reads its values back and stores them;
 //  pull        the step's own pattern without the stencil (see pull_march),
-//              in the 19-array layout and in blocks of 64 nodes.
+//              in the 19-array layout and in blocks of 64 to 4096 nodes;
+//  lds19       the same pattern with 16-byte direct global-to-LDS loads
+//              (pull_lds), and a 19-array stream with 16-byte accesses.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -234,6 +236,86 @@ pull_march(const float* __restrict__ src, float* __restrict__ dst, int nx, int n
   }
 }
 
+// The pull pattern with the loads done by gfx950's direct global-to-LDS
+// loads, 16 bytes per lane (blocks of 1024 nodes, nx = ny = 256, tiles of 4
+// rows, so one tile-plane is one block).  Per plane, for each population a
+// and each of the tile's 4 rows, one wave copies the 1 KiB source row
+// (row y - c_ay of plane z - c_az, unshifted in x) into LDS; after a barrier
+// each thread reads its 19 pulled values (the x shift applied in LDS, with
+// the periodic wrap) into registers.  The next plane's copies are issued
+// before the current plane's stores.  OUT = 0: each thread stores its 19
+// values (4 bytes per lane); OUT = 1: the values pass through LDS and leave
+// as 16-byte stores.
+__device__ constexpr int kRowsA[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+__device__ constexpr int kPlaneA[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+template <int OUT>
+__global__ void __launch_bounds__(1024)
+pull_lds(const float* __restrict__ src, float* __restrict__ dst, int nz, int zc) {
+  constexpr int NX = 256, NY = 256, B = 1024;
+  extern __shared__ __attribute__((aligned(16))) float lds[];
+  float* in = lds;              // [19][4][256]
+  float* out = lds + 19 * B;    // [19][1024] (OUT = 1)
+  const int ty = blockIdx.x % (NY / 4), chunk = blockIdx.x / (NY / 4);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int x = threadIdx.x & (NX - 1), yl = threadIdx.x >> 8;
+  const int z0 = chunk * zc, z1 = z0 + zc;
+  auto issue = [&](int z) {
+    for (int p = wave; p < 19 * 4; p += 16) {
+      const int a = p >> 2, r = p & 3;
+      const int sy = (ty * 4 - kRowsA[a] + r + NY) % NY;
+      const int sz = (z - kPlaneA[a] + nz) % nz;
+      const unsigned node = ((unsigned)sz * NY + sy) * NX;
+      const size_t base = ((size_t)(node / B) * 19 + a) * B + node % B;
+      __builtin_amdgcn_global_load_lds((const void*)(src + base + lane * 4),
+                                       (__attribute__((address_space(3))) void*)(in + p * NX), 16,
+                                       0, 0);
+    }
+  };
+  float cur[19];
+  auto take = [&]() {
+#pragma unroll
+    for (int a = 0; a < 19; ++a) cur[a] = in[(a * 4 + yl) * NX + ((x - PCX[a]) & (NX - 1))];
+  };
+  issue(z0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  take();
+  __syncthreads();
+  for (int z = z0; z < z1; ++z) {
+    if (z + 1 < z1) issue(z + 1);
+    const size_t blk = ((size_t)z * (NY / 4) + ty) * 19 * B;
+    if (OUT == 0) {
+#pragma unroll
+      for (int a = 0; a < 19; ++a)
+        __builtin_nontemporal_store(cur[a] * 1.0001f, &dst[blk + a * B + threadIdx.x]);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 19; ++a) out[a * B + threadIdx.x] = cur[a] * 1.0001f;
+      __syncthreads();
+      const v4f* o4 = reinterpret_cast<const v4f*>(out);
+      v4f* d4 = reinterpret_cast<v4f*>(dst + blk);
+      for (int f = threadIdx.x; f < 19 * B / 4; f += 1024) __builtin_nontemporal_store(o4[f], &d4[f]);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (z + 1 < z1) take();
+    __syncthreads();
+  }
+}
+
+// 19-array stream with 4 consecutive nodes per lane (16-byte loads and
+// stores), one pass: the access width of the copy kernels in the step's
+// 19-stream shape.
+__global__ void stream19x4_onepass(const v4f* __restrict__ a, v4f* __restrict__ b, size_t ps4) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  v4f v[19];
+#pragma unroll
+  for (int q = 0; q < 19; ++q) v[q] = a[q * ps4 + i];
+#pragma unroll
+  for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(v[q] * 1.0001f, &b[q * ps4 + i]);
+}
+
 int main(int argc, char** argv) {
   const char* fam = argc > 1 ? argv[1] : "all";
   auto want = [&](const char* f) { return !std::strcmp(fam, "all") || !std::strcmp(fam, f); };
@@ -368,6 +450,35 @@ int main(int argc, char** argv) {
       if (one(std::integral_constant<int, 0>{}) || one(std::integral_constant<int, 64>{}) ||
           one(std::integral_constant<int, 256>{}) || one(std::integral_constant<int, 1024>{}) ||
           one(std::integral_constant<int, 4096>{}))
+        return 1;
+    }
+  }
+  if (want("lds19")) {
+    // More than 64 KiB of dynamic LDS per work-group must be allowed first.
+    CK(hipFuncSetAttribute(reinterpret_cast<const void*>(&pull_lds<0>),
+                           hipFuncAttributeMaxDynamicSharedMemorySize, 19 * 1024 * 4));
+    CK(hipFuncSetAttribute(reinterpret_cast<const void*>(&pull_lds<1>),
+                           hipFuncAttributeMaxDynamicSharedMemorySize, 2 * 19 * 1024 * 4));
+    const int nz = 512;
+    const size_t n = (size_t)256 * 256 * nz;
+    for (int zc : {128, 8}) {
+      const int grid = 64 * (nz / zc);
+      char name[32];
+      std::snprintf(name, sizeof(name), "pull_lds_out0_z%d", zc);
+      if (run(name, 1024, grid, 2.0 * 19 * n * 4,
+              [&] { pull_lds<0><<<grid, 1024, 19 * 1024 * 4>>>(a, b, nz, zc); }))
+        return 1;
+      std::snprintf(name, sizeof(name), "pull_lds_out1_z%d", zc);
+      if (run(name, 1024, grid, 2.0 * 19 * n * 4,
+              [&] { pull_lds<1><<<grid, 1024, 2 * 19 * 1024 * 4>>>(a, b, nz, zc); }))
+        return 1;
+    }
+    // 2^23 lanes of 4 nodes: the same 2^25 nodes as the float stream.
+    const size_t n4 = n19 / 4, ps4 = n4 + 272;
+    for (int t : {256, 1024}) {
+      const int grid = (int)(n4 / t);
+      if (run("stream19x4_1p", t, grid, 2.0 * 19 * n19 * 4,
+              [&] { stream19x4_onepass<<<grid, t>>>((const v4f*)a, (v4f*)b, ps4); }))
         return 1;
     }
   }
