@@ -210,16 +210,23 @@ PAPER_TABLE = {
 }
 
 
-def paper_ligament(R0, operator, eps=0.1):
+def paper_ligament(R0, operator, eps=0.1, wavelengths=2):
     """Initial density and parameters of the paper's run at radius R0 (Sec. 3,
     Tables 1-2): box L_x = 256 R0/14 along the axis (z here), L_y = L_z =
     96 R0/14, r = R0 + eps R0 cos(4 pi z / L_x) (two wavelengths; the paper's
-    sine differs by a shift along the periodic axis), tanh wall of width 2."""
+    sine differs by a shift along the periodic axis), tanh wall of width 2.
+
+    wavelengths = 1 gives the first half of that box along the axis, one
+    wavelength: the two-wavelength input repeats with period L_x / 2, and a
+    periodic run keeps that period, so the half box holds the same solution
+    at half the cost."""
+    if wavelengths not in (1, 2):
+        raise ValueError("wavelengths must be 1 or 2")
     i = PAPER_RADII.index(R0)
     t = PAPER_TABLE[operator]
-    lx = 256 * R0 // 14
+    lx = 256 * R0 // 14 * wavelengths // 2
     ly = 96 * R0 // 14
-    rho = ligament_density(ly, ly, lx, float(R0), eps, 2, t["rho_v"][i], t["rho_l"][i])
+    rho = ligament_density(ly, ly, lx, float(R0), eps, wavelengths, t["rho_v"][i], t["rho_l"][i])
     return rho, {"R0": R0, "operator": operator, "eps": eps, "nx": ly, "ny": ly, "nz": lx,
                  "G": PAPER_G0, "tau": t["tau"][i], "t_cap": t["t_cap"][i],
                  "rho_l": t["rho_l"][i], "rho_v": t["rho_v"][i], "sigma": t["sigma"][i]}

@@ -128,15 +128,17 @@ class Recorder:
 
 
 def break_time(R0, operator, eps=0.1, every=25, max_tcap=16.0, precision="f32", progress=False,
-               record=None, after_tcap=0.0):
+               record=None, after_tcap=0.0, wavelengths=2):
     """(T_break / t_cap, steps, info) for the paper's run at radius R0.
     With record = a Recorder (or True for the default one), info["record"]
     holds the observables it sampled.  With after_tcap > 0 the run goes on
     for that many capillary times after the break-up and info["drops"] holds
     the liquid bodies along the axis at every sample (see `satellites`); a
     state that turns non-finite ends the continuation and is reported as
-    info["diverged_after_tcap"]."""
-    rho0, info = lbm_inputs.paper_ligament(R0, operator, eps)
+    info["diverged_after_tcap"].  wavelengths = 1 runs half the paper's
+    box along the axis (one wavelength of the perturbation), which holds the
+    same periodic solution at half the cost."""
+    rho0, info = lbm_inputs.paper_ligament(R0, operator, eps, wavelengths)
     return run_to_breakup(rho0, info, operator, every=every, max_tcap=max_tcap,
                           precision=precision, progress=progress, record=record,
                           after_tcap=after_tcap)
@@ -252,6 +254,8 @@ def main():
     ap.add_argument("--after", type=float, default=0.0,
                     help="capillary times to keep running after the break-up (satellites)")
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--wavelengths", type=int, default=2, choices=[1, 2],
+                    help="1: half the paper's box along the axis (one wavelength, same solution)")
     args = ap.parse_args()
     out = []
     for op in args.operators.split(","):
@@ -259,8 +263,9 @@ def main():
             for eps in (float(e) for e in args.eps.split(",")):
                 t, steps, info = break_time(R0, op, eps, args.every, precision=args.precision,
                                             progress=True, record=bool(args.record),
-                                            after_tcap=args.after)
+                                            after_tcap=args.after, wavelengths=args.wavelengths)
                 rec = {"operator": op, "R0": R0, "eps": eps, "precision": args.precision,
+                       "wavelengths": args.wavelengths,
                        "T_break_over_tcap": t,
                        "steps": steps, "box": [info["nx"], info["ny"], info["nz"]]}
                 if "diverged_after_tcap" in info:

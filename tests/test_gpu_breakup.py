@@ -93,3 +93,28 @@ def test_float32_and_float64_break_at_the_same_step(op):
     t64, s64, _ = breakup.break_time(14, op, precision="f64", every=5)
     print("%s R0=14: f32 %d steps, f64 %d steps" % (op, s32, s64), flush=True)
     assert abs(s32 - s64) <= 5
+
+
+@pytest.mark.parametrize("op", ["mrt", "srt"])
+def test_one_wavelength_box_holds_the_same_run(op):
+    """Half the paper's box along the axis (one wavelength) against the whole
+    two-wavelength box at R0 = 14: the same break-up step and the same r(z)
+    on the first half at every sample (the two inputs differ only by the
+    rounding of cos at shifted arguments)."""
+    import numpy as np
+    from paper_1905_09554_amd import breakup
+    runs = {}
+    for wl in (2, 1):
+        rho0, info = lbm_inputs.paper_ligament(14, op, 0.1, wavelengths=wl)
+        rec = breakup.Recorder(info, silhouette_tstar=(), velocity_tstar=())
+        t, steps, info = breakup.break_time(14, op, record=rec, wavelengths=wl)
+        runs[wl] = (steps, info["record"]["r_of_z"])
+    print("%s R0=14: two wavelengths %d steps, one %d steps" % (op, runs[2][0], runs[1][0]),
+          flush=True)
+    assert runs[1][0] == runs[2][0]
+    r2, r1 = runs[2][1], runs[1][1]
+    half = r1.shape[1]
+    assert r2.shape[1] == 2 * half
+    err = float(np.abs(r2[:, :half] - r1).max())
+    print("  max |dr| over all samples: %.2e" % err, flush=True)
+    assert err < 1e-4
