@@ -24,10 +24,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# What a plain float4 device copy reaches on MI355X (hand-written probe,
-# paper_1905_09554_amd/csrc/hbm_probe.hip): the practical ceiling of a
-# streaming kernel, reported beside the published peak.
-COPY_CEILING_GBS = 5350.0
+# Measured ceilings on MI355X (hand-written probe,
+# paper_1905_09554_amd/csrc/hbm_probe.hip), reported beside the published
+# peak: the fastest plain copy (one pass, 16 bytes per lane, one 256-thread
+# group per 4 KiB) and the step's own access pattern without its stencil
+# (19 pulled loads and 19 stores per node, 1024-thread groups of 256 x 4
+# tiles marching 128 planes, populations in blocks of 1024 nodes).
+COPY_CEILING_GBS = 6324.0
+PULL_PATTERN_GBS = 5294.0
 WORKLOAD = "ligament_256x256x1024_mrt_f32"
 METRIC = "MLUPS & % HBM peak, D3Q19 Shan-Chen FP32 vs FP64; adjoint/forward cost ratio"
 DIAG_EVERY = 100
@@ -487,6 +491,8 @@ def main():
         "roofline": f32["roofline"],
         "copy_ceiling": {"gbs": COPY_CEILING_GBS,
                          "frac": round(f32["roofline"]["achieved"] / COPY_CEILING_GBS, 4)},
+        "pull_pattern_ceiling": {"gbs": PULL_PATTERN_GBS,
+                                 "frac": round(f32["roofline"]["achieved"] / PULL_PATTERN_GBS, 4)},
         "kernel_ms": round(f32["kernel_ms"], 4),
         # Step kernel alone (HIP events, no diagnostics), and the measured HBM
         # bytes per node-step from the counter runs.
