@@ -99,8 +99,8 @@ typedef struct lbsc_tuning {
   int32_t threads;     /* work-group size of the fused step: 256, 512, 1024   */
   int32_t z_chunk;     /* planes marched per work-group (>= 1)                */
   int32_t xcd_remap;   /* 1: map neighbouring tiles onto one XCD (L2), 0: off;
-                          < 0: the default (1, except 0 for float64 boxes
-                          of more than one wave of work-groups)             */
+                          < 0: the default (1 for a single box, 0 for a
+                          batch)                                            */
   int32_t block_y;     /* rows per tile; 0 = as many as the work-group holds  */
   int32_t pop_pad;     /* padding between population arrays, <= 65536 (only
                           for one array per population; see above)        */

@@ -284,17 +284,17 @@ void chunk_and_order(const lbsc_params* p, int32_t n, lbsc_tuning* t) {
   if (zc < 1) zc = 1;
   if (zc > zmax) zc = zmax;
   t->z_chunk = (int)zc;
-  // float64 over more than one wave of groups (two 256-thread groups per CU):
-  // plain dispatch order beats XCD-local tile ranges (measured 14.15 against
-  // 13.87 GLUPS on 256 x 256 x 1024 MRT, eight waves); within one wave the
-  // XCD-local ranges win (32 x 32 x 64: 7.2 against 5.9 GLUPS).
-  // Batches run in plain dispatch order as well: consecutive entries of the
-  // tile table are neighbouring tiles of one member, so plain order keeps
-  // the groups in flight on one contiguous stretch of memory; XCD-local
-  // ranges cut the L2-missing halo reads (fetch 1.41 -> 1.11 x the
-  // algorithmic reads, the rest served by the memory-side cache) but spread
-  // the groups over eight stretches and run slower (14.47 against 14.27 ms).
-  t->xcd_remap = ((p[0].precision == LBSC_F64 && (columns + zc - 1) / zc > 512) || n > 1) ? 0 : 1;
+  // Single boxes take XCD-local tile ranges: in both precisions they beat
+  // plain dispatch order with the populations stored in blocks (256 x 256 x
+  // 1024 MRT, float64 over eight waves of groups: 4.20 against 4.43 ms;
+  // float32 in one wave: 2.08 against 2.12).  Batches run in plain dispatch
+  // order: consecutive entries of the tile table are neighbouring tiles of
+  // one member, so plain order keeps the groups in flight on one contiguous
+  // stretch of memory; XCD-local ranges cut the L2-missing halo reads (fetch
+  // 1.41 -> 1.11 x the algorithmic reads, the rest served by the memory-side
+  // cache) but spread the groups over eight stretches and run slower (14.47
+  // against 14.27 ms).
+  t->xcd_remap = n > 1 ? 0 : 1;
 }
 
 lbsc_tuning default_tuning(const lbsc_params* p, int32_t n) {

@@ -156,7 +156,7 @@ def test_binding_structs_match_the_header_layout(tmp_path):
 @pytest.mark.parametrize("box,coll,prec,expect", [
     # (threads, block_x, block_y, z_chunk, xcd_remap)
     ((256, 256, 1024), "mrt", "f32", (1024, 256, 4, 256, 1)),   # one wave of 256 groups
-    ((256, 256, 1024), "mrt", "f64", (256, 64, 4, 64, 0)),      # eight waves: dispatch order
+    ((256, 256, 1024), "mrt", "f64", (256, 64, 4, 64, 1)),      # eight waves, XCD-local ranges
     ((128, 128, 512), "bgk", "f64", (256, 64, 4, 64, 1)),       # one wave: XCD-local ranges
     ((64, 64, 256), "mrt", "f32", (1024, 64, 16, 4, 1)),
     ((32, 32, 64), "bgk", "f64", (256, 32, 8, 1, 1)),           # small box: one-plane chunks
