@@ -29,7 +29,12 @@ def candidates(nx, precision, nodes=None):
     """Launch shapes worth timing for a box of row length nx (and, when
     given, `nodes` in all: boxes under 16 M nodes also try the short
     z-chunks that give them enough work-groups)."""
-    widths = sorted({nx} | {w for w in (64, 128, 192, 256, 384, 512) if w < nx})
+    # Multiples of 64 columns, whole rows, and the even splits of a row into
+    # 2-6 tiles whose width is a multiple of 16 nodes (no ragged last tile,
+    # and tile edges on 64-byte lines in float32).
+    widths = sorted({nx} | {w for w in (64, 128, 192, 256, 384, 512) if w < nx}
+                    | {nx // k for k in range(2, 7)
+                       if nx % k == 0 and (nx // k) % 16 == 0 and nx // k >= 64})
     out = []
     for threads, npt in itertools.product((256, 512, 1024), (1, 2)):
         if precision == "f64" and (threads == 1024 or npt == 2):

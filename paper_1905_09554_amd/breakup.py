@@ -18,7 +18,7 @@ import torch
 
 import lbm_inputs
 
-from . import lbsc
+from . import lbsc, tuning
 
 
 def params_for(info, operator, precision="f32"):
@@ -150,7 +150,9 @@ def run_to_breakup(rho0, info, operator, every=25, max_tcap=16.0, precision="f32
     (nx, ny, nz), G, tau, rho_l, rho_v, t_cap and R0 (and eps for the
     progress lines).  Same return values."""
     R0, eps = info["R0"], info.get("eps", float("nan"))
-    sim = lbsc.Simulation(rho0, params_for(info, operator, precision))
+    prm = params_for(info, operator, precision)
+    sim = lbsc.Simulation(rho0, prm)
+    tuning.apply(sim, prm)  # a measured launch shape for this box, if one is cached
     rec = Recorder(info) if record is True else (record or None)
     rho_mid = 0.5 * (info["rho_l"] + info["rho_v"])
     max_steps = int(max_tcap * info["t_cap"])

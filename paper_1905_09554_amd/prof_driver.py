@@ -7,7 +7,8 @@ Runs the benchmark box (256 x 256 x 1024 ligament, MRT, the launch shape the
 benchmark uses) for a few steps, then a plain device-to-device copy of a known
 size whose counters calibrate FETCH_SIZE and WRITE_SIZE.  With --adjoint it
 runs the adjoint workload instead (64 x 64 x 256 MRT, 4000 steps, checkpoints
-every 200, loss r_min): forward, loss gradient and backward, once.  With
+every 200, loss r_min; --adjoint-steps K for a shorter run followed by the
+calibration copy): forward, loss gradient and backward, once.  With
 --batch it runs the 64-ligament dispersion batch (3.9e8 nodes, FP32 BGK) for
 --steps steps with one launch per step, then the same calibration copy (the
 persistent cooperative form is timed with HIP events by the benchmark, not
@@ -32,6 +33,9 @@ def main():
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--adjoint", action="store_true",
                     help="run the adjoint workload (forward with checkpoints, backward) instead")
+    ap.add_argument("--adjoint-steps", type=int, default=None,
+                    help="steps of the adjoint run (default: the workload's 4000); with this "
+                         "option the calibration copy follows")
     ap.add_argument("--batch", action="store_true",
                     help="run the 64-ligament batch instead, one launch per step")
     ap.add_argument("--small", action="store_true",
@@ -80,12 +84,16 @@ def main():
         prm = lbsc.make_params(nx, ny, nz, collision=info["collision"], precision=args.precision,
                                G=info["G"], tau=info["tau"])
         sim = lbsc.Simulation(rho0, prm)
-        sim.adjoint_forward(info["steps"], info["checkpoint_every"])
+        steps = info["steps"] if args.adjoint_steps is None else args.adjoint_steps
+        sim.adjoint_forward(steps, min(info["checkpoint_every"], steps))
         rhobar, rmin = sim.rmin_gradient(info["rho_v"], info["rho_l"])
         _, dG, dtau = sim.adjoint_backward(rhobar)
         torch.cuda.synchronize()
-        print("adjoint done", name, args.precision, rmin, dG, dtau, flush=True)
+        print("adjoint done", name, args.precision, steps, rmin, dG, dtau, flush=True)
         sim.close()
+        del sim
+        if args.adjoint_steps is not None:
+            calibration_copy()
         return
 
     rho0, info = lbm_inputs.workload_density(args.workload)

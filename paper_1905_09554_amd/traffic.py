@@ -68,14 +68,45 @@ def reduce_counters(fetch_rows, write_rows, precision, nodes):
     }
 
 
+def by_kernel(fetch_rows, write_rows, nodes):
+    """Mean scaled bytes per dispatch of every kernel in the two counter
+    runs (the last copy dispatch calibrates each counter), and per node."""
+    _, f_copy, _ = _per_kernel([("k_step", 0.0)] + fetch_rows)
+    _, w_copy, _ = _per_kernel([("k_step", 0.0)] + write_rows)
+    kib = COPY_BYTES / 1024.0
+    out = {}
+    for rows, copy, key in ((fetch_rows, f_copy, "fetch"), (write_rows, w_copy, "write")):
+        groups = {}
+        for name, v in rows:
+            short = name.replace("lbsc::(anonymous namespace)::", "").replace("void ", "")
+            short = short.split("(")[0]
+            groups.setdefault(short, []).append(v)
+        for short, vals in groups.items():
+            b = statistics.mean(vals) * kib / copy * 1024.0
+            e = out.setdefault(short, {"dispatches": len(vals)})
+            e[key + "_bytes"] = b
+            e[key + "_bytes_per_node"] = b / nodes
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
-    ap.add_argument("--precision", required=True, choices=["f32", "f64"])
+    ap.add_argument("--precision", choices=["f32", "f64"])
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--nodes", type=int, default=256 * 256 * 1024)
+    ap.add_argument("--by-kernel", action="store_true",
+                    help="print the scaled bytes of every kernel (per dispatch and per node); "
+                         "writes no file")
     args = ap.parse_args()
+
+    if args.by_kernel:
+        rec = by_kernel(_rows(args.fetch, "FETCH_SIZE"), _rows(args.write, "WRITE_SIZE"), args.nodes)
+        print(json.dumps(rec, indent=1))
+        return
+    if args.precision is None:
+        ap.error("--precision is required unless --by-kernel is given")
 
     import sys
     sys.path.insert(0, ROOT)

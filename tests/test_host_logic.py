@@ -26,7 +26,7 @@ def test_tau_for_ohnesorge_inverts_eq_oh_tcap():
 def test_autotune_candidates_are_valid_shapes():
     from paper_1905_09554_amd import autotune
     for nx, prec, nodes in ((256, "f32", None), (256, "f64", None), (32, "f64", 65536),
-                            (600, "f32", None)):
+                            (600, "f32", None), (672, "f32", None)):
         cands = autotune.candidates(nx, prec, nodes=nodes)
         assert cands
         assert any(c["z_chunk"] < 16 for c in cands) == (nodes is not None)
@@ -34,9 +34,14 @@ def test_autotune_candidates_are_valid_shapes():
             cap = c["threads"] * c["nodes_per_thread"]
             assert c["block_x"] <= min(nx, cap)
             if c["block_x"] < nx:
-                assert c["block_x"] % 64 == 0 and 2 * c["block_x"] <= cap
+                even_split = nx % c["block_x"] == 0 and c["block_x"] % 16 == 0
+                assert (c["block_x"] % 64 == 0 or even_split) and 2 * c["block_x"] <= cap
+                assert c["block_x"] >= 64
             if prec == "f64":
                 assert c["threads"] <= 512 and c["nodes_per_thread"] == 1
+    # A 672-node row also splits into 2, 3 and 6 even tiles (336, 224, 112).
+    widths = {c["block_x"] for c in autotune.candidates(672, "f32")}
+    assert {336, 224, 112} <= widths
 
 
 def test_growth_fit_recovers_an_exponential():
