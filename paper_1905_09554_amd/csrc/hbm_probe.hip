@@ -2,7 +2,7 @@
 // It is the denominator next to the 8 TB/s datasheet peak when the step's
 // achieved bandwidth is compared.  Prints one line per kernel and launch shape.
 //
-//   paper_1905_09554_amd/hbm_probe [gridstride|onepass|stream|lds|pull|lds19|all]
+//   paper_1905_09554_amd/hbm_probe [gridstride|onepass|stream|lds|pull|shift|lds19|all]
 //
 // Families (every kernel moves a known number of bytes, timed over 10 launches
 // after a warm-up with HIP events):
@@ -25,6 +25,9 @@
 //              lane reads its values back and stores them;
 //  pull        the step's own pattern without the stencil (see pull_march),
 //              in the 19-array layout and in blocks of 64 to 4096 nodes;
+//  shift       the pull pattern in blocks of 1024 nodes with some of its x, y,
+//              z shifts switched off, and with the x shift taken across lanes
+//              from aligned loads (checked to store what the plain form does);
 //  lds19       the same pattern with 16-byte direct global-to-LDS loads
 //              (pull_lds), and a 19-array stream with 16-byte accesses.
 #include <hip/hip_runtime.h>
@@ -204,7 +207,10 @@ __device__ inline size_t paddr(int a, unsigned i, size_t ps) {
   return (size_t)a * ps + i;
 }
 
-template <int BLK>
+// MASK switches the three shifts on (bit 0: x, bit 1: y, bit 2: z); a shift
+// that is off reads the centre node's row, plane or column instead, which
+// shows what each shift costs (7: the step's pattern).
+template <int BLK, int MASK = 7>
 __global__ void __launch_bounds__(1024)
 pull_march(const float* __restrict__ src, float* __restrict__ dst, int nx, int ny, int nz,
            int zc, size_t ps) {
@@ -221,7 +227,9 @@ pull_march(const float* __restrict__ src, float* __restrict__ dst, int nx, int n
                             (unsigned)(z == nz - 1 ? 0 : z + 1) * plane};
 #pragma unroll
     for (int a = 0; a < 19; ++a) {
-      const unsigned i = zo[1 - PCZ[a]] + yo[1 - PCY[a]] + xo[1 - PCX[a]];
+      const int cx = (MASK & 1) ? PCX[a] : 0, cy = (MASK & 2) ? PCY[a] : 0;
+      const int cz = (MASK & 4) ? PCZ[a] : 0;
+      const unsigned i = zo[1 - cz] + yo[1 - cy] + xo[1 - cx];
       v[a] = src[paddr<BLK>(a, i, ps)];
     }
   };
@@ -234,6 +242,89 @@ pull_march(const float* __restrict__ src, float* __restrict__ dst, int nx, int n
 #pragma unroll
     for (int a = 0; a < 19; ++a) cur[a] = nxt[a];
   }
+}
+
+// The pull pattern (all three shifts) with every load aligned to the
+// node's own column: a population with c_x = +1 takes the value of the lane
+// to its left by a DPP wave shift (wave_shr:1), c_x = -1 that of the lane to
+// its right (wave_shl:1), and the one lane at the wave's edge loads its value
+// itself.  Each wave covers 64 consecutive nodes of one row (nx = 256).
+// The lane whose source lies outside the wave (lane 0 for wave_shr, lane 63
+// for wave_shl) keeps `old`: with bound_ctrl off, DPP does not write it.
+__device__ inline float lane_from_left(float v, float old) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                               __builtin_bit_cast(int, v),
+                                                               0x138, 0xF, 0xF, false));
+}
+__device__ inline float lane_from_right(float v, float old) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                               __builtin_bit_cast(int, v),
+                                                               0x130, 0xF, 0xF, false));
+}
+
+template <int BLK>
+__global__ void __launch_bounds__(1024)
+pull_dpp(const float* __restrict__ src, float* __restrict__ dst, int nx, int ny, int nz, int zc,
+         size_t ps) {
+  const int tiles_y = ny / 4;
+  const int ty = blockIdx.x % tiles_y, chunk = blockIdx.x / tiles_y;
+  const int x = threadIdx.x % nx, y = ty * 4 + threadIdx.x / nx;
+  const int lane = threadIdx.x & 63;
+  const int z0 = chunk * zc, z1 = z0 + zc;
+  const unsigned plane = (unsigned)nx * ny;
+  // The wave's first and last column and their outer neighbours (periodic).
+  const int xf = x - lane, xl = xf + 63;
+  const int left = xf == 0 ? nx - 1 : xf - 1, right = xl == nx - 1 ? 0 : xl + 1;
+  const int yo[3] = {(y == 0 ? ny - 1 : y - 1) * nx, y * nx, (y == ny - 1 ? 0 : y + 1) * nx};
+  float cur[19], nxt[19], edge[19];
+  // Issues the plane's aligned loads and the wave-edge loads; the lane
+  // shifts are applied by fix() once the values have arrived.
+  auto load = [&](int z) {
+    const unsigned zo[3] = {(unsigned)(z == 0 ? nz - 1 : z - 1) * plane, (unsigned)z * plane,
+                            (unsigned)(z == nz - 1 ? 0 : z + 1) * plane};
+#pragma unroll
+    for (int a = 0; a < 19; ++a) {
+      const unsigned row = zo[1 - PCZ[a]] + yo[1 - PCY[a]];
+      nxt[a] = src[paddr<BLK>(a, row + x, ps)];
+      if (PCX[a] != 0) {
+        const unsigned e = __builtin_amdgcn_readfirstlane(row + (PCX[a] > 0 ? left : right));
+        edge[a] = src[paddr<BLK>(a, e, ps)];
+      }
+    }
+  };
+  auto fix = [&]() {
+#pragma unroll
+    for (int a = 0; a < 19; ++a) {
+      if (PCX[a] > 0) nxt[a] = lane_from_left(nxt[a], edge[a]);
+      if (PCX[a] < 0) nxt[a] = lane_from_right(nxt[a], edge[a]);
+    }
+  };
+  load(z0);
+  fix();
+  for (int z = z0; z < z1; ++z) {
+#pragma unroll
+    for (int a = 0; a < 19; ++a) cur[a] = nxt[a];
+    load(z + 1 < nz ? z + 1 : 0);
+    const unsigned i = (unsigned)z * plane + yo[1] + x;
+#pragma unroll
+    for (int a = 0; a < 19; ++a) __builtin_nontemporal_store(cur[a] * 1.0001f, &dst[paddr<BLK>(a, i, ps)]);
+    fix();
+  }
+}
+
+__global__ void fill_pattern(float* __restrict__ a, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    a[i] = (float)((unsigned)(i * 2654435761u) >> 8) * 1e-6f;
+}
+
+__global__ void count_diff(const float* __restrict__ p, const float* __restrict__ q, size_t n,
+                           unsigned* __restrict__ bad) {
+  unsigned k = 0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    k += __float_as_uint(p[i]) != __float_as_uint(q[i]);
+  if (k) atomicAdd(bad, k);
 }
 
 // The pull pattern with the loads done by gfx950's direct global-to-LDS
@@ -450,6 +541,47 @@ int main(int argc, char** argv) {
       if (one(std::integral_constant<int, 0>{}) || one(std::integral_constant<int, 64>{}) ||
           one(std::integral_constant<int, 256>{}) || one(std::integral_constant<int, 1024>{}) ||
           one(std::integral_constant<int, 4096>{}))
+        return 1;
+    }
+  }
+  if (want("shift")) {
+    // The pull pattern in blocks of 1024 nodes with shifts switched off, and
+    // with the x shift taken across lanes; first, that the lane-shift form
+    // stores exactly what the plain form stores.
+    const int nx = 256, ny = 256, nz = 512;
+    const size_t n = (size_t)nx * ny * nz, ps = n, L = 19 * n;
+    float* c;
+    CK(hipMalloc(&c, L * 4));
+    fill_pattern<<<65536, 256>>>(a, L);
+    const int g8 = (ny / 4) * (nz / 8);
+    pull_march<1024, 7><<<g8, 1024>>>(a, c, nx, ny, nz, 8, ps);
+    pull_dpp<1024><<<g8, 1024>>>(a, b, nx, ny, nz, 8, ps);
+    CK(hipMemset(o, 0, 64));
+    count_diff<<<65536, 256>>>(b, c, L, (unsigned*)o);
+    CK(hipGetLastError());
+    unsigned bad = 0;
+    CK(hipMemcpy(&bad, o, 4, hipMemcpyDeviceToHost));
+    std::printf("pull_dpp against pull_march: %u of %zu stored values differ\n", bad, L);
+    std::fflush(stdout);
+    CK(hipFree(c));
+    for (int zc : {128, 8}) {
+      const int grid = (ny / 4) * (nz / zc);
+      const double traffic = 2.0 * 19 * n * 4;
+      auto one = [&](auto mc) -> int {
+        constexpr int M = decltype(mc)::value;
+        char name[32];
+        std::snprintf(name, sizeof(name), "pull_mask%d_z%d", M, zc);
+        return run(name, 1024, grid, traffic,
+                   [&] { pull_march<1024, M><<<grid, 1024>>>(a, b, nx, ny, nz, zc, ps); });
+      };
+      if (one(std::integral_constant<int, 7>{}) || one(std::integral_constant<int, 6>{}) ||
+          one(std::integral_constant<int, 5>{}) || one(std::integral_constant<int, 3>{}) ||
+          one(std::integral_constant<int, 1>{}) || one(std::integral_constant<int, 0>{}))
+        return 1;
+      char name[32];
+      std::snprintf(name, sizeof(name), "pull_dpp_z%d", zc);
+      if (run(name, 1024, grid, traffic,
+              [&] { pull_dpp<1024><<<grid, 1024>>>(a, b, nx, ny, nz, zc, ps); }))
         return 1;
     }
   }
