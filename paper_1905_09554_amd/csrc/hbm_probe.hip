@@ -2,7 +2,7 @@
 // It is the denominator next to the 8 TB/s datasheet peak when the step's
 // achieved bandwidth is compared.  Prints one line per kernel and launch shape.
 //
-//   paper_1905_09554_amd/hbm_probe [gridstride|onepass|stream|lds|pull|shift|lds19|all]
+//   paper_1905_09554_amd/hbm_probe [gridstride|onepass|stream|lds|pull|shift|wide|lds19|all]
 //
 // Families (every kernel moves a known number of bytes, timed over 10 launches
 // after a warm-up with HIP events):
@@ -28,6 +28,8 @@
 //  shift       the pull pattern in blocks of 1024 nodes with some of its x, y,
 //              z shifts switched off, and with the x shift taken across lanes
 //              from aligned loads (checked to store what the plain form does);
+//  wide        the pull pattern with 2 or 4 consecutive nodes per lane (8- and
+//              16-byte accesses) against one node per lane;
 //  lds19       the same pattern with 16-byte direct global-to-LDS loads
 //              (pull_lds), and a 19-array stream with 16-byte accesses.
 #include <hip/hip_runtime.h>
@@ -312,6 +314,48 @@ pull_dpp(const float* __restrict__ src, float* __restrict__ dst, int nx, int ny,
   }
 }
 
+// The pull pattern with W consecutive nodes of a row per lane (blocks of
+// 1024 nodes, nx = 256): 19 loads of W values (8 or 16 bytes; the x-shifted
+// ones start one node off, at 4-byte alignment) and 19 aligned stores of W
+// values per lane and plane.  Bandwidth only: a vector that would wrap
+// around the row is clamped into it, so the values at the row's ends are not
+// the periodic ones.
+template <int W, int NT>
+__global__ void __launch_bounds__(NT)
+pull_wide(const float* __restrict__ src, float* __restrict__ dst, int nx, int ny, int nz,
+          int zc) {
+  typedef float vw __attribute__((ext_vector_type(W)));
+  const int rows = NT * W / nx;
+  const int tiles_y = ny / rows;
+  const int ty = blockIdx.x % tiles_y, chunk = blockIdx.x / tiles_y;
+  const int x = (threadIdx.x * W) % nx, y = ty * rows + (threadIdx.x * W) / nx;
+  const int z0 = chunk * zc, z1 = z0 + zc;
+  const unsigned plane = (unsigned)nx * ny;
+  const int yo[3] = {(y == 0 ? ny - 1 : y - 1) * nx, y * nx, (y == ny - 1 ? 0 : y + 1) * nx};
+  vw cur[19], nxt[19];
+  auto load = [&](int z, vw(&v)[19]) {
+    const unsigned zo[3] = {(unsigned)(z == 0 ? nz - 1 : z - 1) * plane, (unsigned)z * plane,
+                            (unsigned)(z == nz - 1 ? 0 : z + 1) * plane};
+#pragma unroll
+    for (int a = 0; a < 19; ++a) {
+      const int xs = min(max(x - PCX[a], 0), nx - W);
+      const unsigned i = zo[1 - PCZ[a]] + yo[1 - PCY[a]] + xs;
+      __builtin_memcpy(&v[a], src + paddr<1024>(a, i, 0), sizeof(vw));
+    }
+  };
+  load(z0, cur);
+  for (int z = z0; z < z1; ++z) {
+    load(z + 1 < nz ? z + 1 : 0, nxt);
+    const unsigned i = (unsigned)z * plane + yo[1] + x;
+#pragma unroll
+    for (int a = 0; a < 19; ++a)
+      __builtin_nontemporal_store(cur[a] * 1.0001f,
+                                  reinterpret_cast<vw*>(dst + paddr<1024>(a, i, 0)));
+#pragma unroll
+    for (int a = 0; a < 19; ++a) cur[a] = nxt[a];
+  }
+}
+
 __global__ void fill_pattern(float* __restrict__ a, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)
@@ -582,6 +626,36 @@ int main(int argc, char** argv) {
       std::snprintf(name, sizeof(name), "pull_dpp_z%d", zc);
       if (run(name, 1024, grid, traffic,
               [&] { pull_dpp<1024><<<grid, 1024>>>(a, b, nx, ny, nz, zc, ps); }))
+        return 1;
+    }
+  }
+  if (want("wide")) {
+    // The pull pattern with 2 or 4 nodes per lane against 1 (same box).
+    const int nx = 256, ny = 256, nz = 512;
+    const size_t n = (size_t)nx * ny * nz;
+    const double traffic = 2.0 * 19 * n * 4;
+    for (int zc : {128, 8}) {
+      char name[40];
+      {
+        const int grid = (ny / 4) * (nz / zc);
+        std::snprintf(name, sizeof(name), "pull_w1_t1024_z%d", zc);
+        if (run(name, 1024, grid, traffic,
+                [&] { pull_march<1024, 7><<<grid, 1024>>>(a, b, nx, ny, nz, zc, n); }))
+          return 1;
+      }
+      auto one = [&](auto wc, auto tc) -> int {
+        constexpr int W = decltype(wc)::value, T = decltype(tc)::value;
+        const int rows = T * W / nx;
+        const int grid = (ny / rows) * (nz / zc);
+        std::snprintf(name, sizeof(name), "pull_w%d_t%d_z%d", W, T, zc);
+        return run(name, T, grid, traffic,
+                   [&] { pull_wide<W, T><<<grid, T>>>(a, b, nx, ny, nz, zc); });
+      };
+      if (one(std::integral_constant<int, 2>{}, std::integral_constant<int, 1024>{}) ||
+          one(std::integral_constant<int, 2>{}, std::integral_constant<int, 512>{}) ||
+          one(std::integral_constant<int, 2>{}, std::integral_constant<int, 256>{}) ||
+          one(std::integral_constant<int, 4>{}, std::integral_constant<int, 512>{}) ||
+          one(std::integral_constant<int, 4>{}, std::integral_constant<int, 256>{}))
         return 1;
     }
   }
