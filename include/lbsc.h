@@ -237,8 +237,8 @@ int lbsc_member_set_state(lbsc_ctx* c, int32_t member, const void* host, size_t 
  */
 
 /* Workspace bytes for nsteps steps with checkpoints every segment steps
- * (about (nsteps/segment + segment + 3) lattices plus segment density
- * fields); 0 if invalid. */
+ * (about (nsteps/segment + segment + 3) lattices plus segment psi
+ * fields, the psi(rho) each recomputed step's forces used); 0 if invalid. */
 size_t lbsc_adjoint_workspace_bytes(const lbsc_params* p, int64_t nsteps, int32_t segment);
 
 /* Runs nsteps steps from the initial state (step counter 0), saving a

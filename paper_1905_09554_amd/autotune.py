@@ -3,6 +3,7 @@
     python -m paper_1905_09554_amd.autotune [--workload NAME | --box NX,NY,NZ]
                                             [--precision f32,f64] [--collision mrt]
                                             [--steps K] [--out FILE]
+    python -m paper_1905_09554_amd.autotune --batch [--steps K] [--out FILE]
 
 For one box (a workload of lbm_inputs.WORKLOADS), times the step over a grid
 of launch shapes: work-group size, nodes per thread, tile width (whole rows
@@ -10,7 +11,9 @@ or multiples of 64 columns), z chunk and the XCD-aware tile order.  Each
 candidate runs K steps after a short warm-up, timed with HIP events on the
 library's stream.  The fastest shape is stored under the key of
 tuning.key(params) together with its MLUPS and the library default's, so
-the benchmark and the full-size tests use what was measured fastest.  The
+the benchmark and the full-size tests use what was measured fastest.  With
+--batch it tunes the dispersion batch instead (work-group size, z chunk,
+tile order, and the persistent form), stored under tuning.batch_key.  The
 state of the box is the workload's own input; timing does not depend on it
 beyond the first steps.
 """
@@ -132,6 +135,70 @@ def tune(workload, precision, collision, steps=20, progress=True, out=None, box=
     return entry
 
 
+def batch_candidates():
+    """Launch shapes worth timing for a batch of small boxes: work-group
+    size, z chunk and tile order (tiles are whole rows of each member, the
+    default for boxes this narrow)."""
+    return [dict(threads=threads, z_chunk=zc, xcd_remap=remap, persistent=0)
+            for threads in (256, 512, 1024) for zc in (2, 4, 8, 16, 32, 64)
+            for remap in (0, 1)]
+
+
+def tune_batch(workload=None, steps=5, progress=True, out=None):
+    """Times the dispersion batch (every member stepped together) over
+    batch_candidates(), then re-times the four fastest, the library default
+    and the fastest in the persistent form (one cooperative launch for all
+    steps) five times longer, and stores the best under
+    tuning.batch_key(workload, precision)."""
+    import torch
+    from . import dispersion, lbsc, tuning
+
+    workload = workload or dispersion.WORKLOAD
+    sweep = dispersion.make_sweep(seed=0, workload=workload)
+    params = dispersion.member_params(sweep)
+    b = lbsc.Batch([m["rho0"] for m in sweep["members"]], params)
+    n = sum(m["nx"] * m["ny"] * m["nz"] for m in sweep["members"])
+    default_shape = b.get_tuning()
+    tried = []
+    for c in batch_candidates():
+        try:
+            b.set_tuning(**c)
+        except lbsc.LbscError:
+            continue
+        t = time_shape(b, steps)
+        shape = b.get_tuning()
+        tried.append((t, shape))
+        if progress:
+            print("  %s: %s %.0f MLUPS" % (workload, shape, n / t / 1e6), flush=True)
+    tried.sort(key=lambda x: x[0])
+    finalists = [default_shape] + [shape for _, shape in tried[:4]]
+    finalists.append(dict(tried[0][1], persistent=1))
+    timed = []
+    for shape in finalists:
+        b.set_tuning(**shape)
+        timed.append((time_shape(b, 5 * steps), b.get_tuning()))
+        if progress:
+            print("  final %s %.0f MLUPS" % (timed[-1][1], n / timed[-1][0] / 1e6), flush=True)
+    default = timed[0][0]
+    best = min(timed, key=lambda x: x[0])
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    entry = {"tuning": best[1], "mlups": n / best[0] / 1e6,
+             "default": {"tuning": default_shape, "mlups": n / default / 1e6},
+             "steps_timed": steps, "candidates": len(tried),
+             "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+    path = out or tuning._CACHE
+    cache = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            cache = json.load(fh)
+    cache[tuning.batch_key(workload, sweep["precision"])] = entry
+    with open(path, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    return entry
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="ligament_256x256x1024_mrt_f32")
@@ -142,7 +209,14 @@ def main():
                     help="cache file to update (default: the package's tuning_cache.json)")
     ap.add_argument("--box", default=None,
                     help="nx,ny,nz of a box to tune instead of a named workload")
+    ap.add_argument("--batch", action="store_true",
+                    help="tune the dispersion batch (all members in one launch) instead")
     args = ap.parse_args()
+    if args.batch:
+        e = tune_batch(steps=args.steps, out=args.out)
+        print(json.dumps({"workload": "batch", "best": e["tuning"], "mlups": round(e["mlups"], 1),
+                          "default_mlups": round(e["default"]["mlups"], 1)}), flush=True)
+        return
     box = tuple(int(v) for v in args.box.split(",")) if args.box else None
     for prec in args.precision.split(","):
         e = tune(args.workload, prec, args.collision, args.steps, out=args.out, box=box)

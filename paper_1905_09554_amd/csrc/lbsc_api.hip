@@ -38,16 +38,16 @@ struct Member {
 };
 
 // Caller workspace of the adjoint: checkpoints of the forward run, the
-// lattices and densities of one recomputed segment, the adjoint state.
+// lattices and psi fields of one recomputed segment, the adjoint state.
 struct AdjWork {
   bool ready = false;
   int64_t nsteps = 0;
   int32_t segment = 0;
   int ncp = 0;
-  size_t lat_bytes = 0, rho_bytes = 0;
+  size_t lat_bytes = 0, psi_bytes = 0;
   char* cp = nullptr;    // ncp lattices
   char* ring = nullptr;  // segment + 1 lattices
-  char* rho = nullptr;   // segment densities
+  char* psi = nullptr;   // psi of every step of the segment
   char* P[2] = {nullptr, nullptr};
   char* R[2] = {nullptr, nullptr};
   char* psi_fbar = nullptr;    // 3 n values: psi(x) dL/dF(x)
@@ -249,7 +249,7 @@ lbsc::StepArgs make_args(const lbsc_params& p, const lbsc_tuning& t, long long p
   a.s_bulk = p.s_bulk;
   a.s_ghost = p.s_ghost;
   a.rho_ref = p.precision == LBSC_F64 ? 0.0 : p.rho_ref;
-  a.rho_out = nullptr;
+  a.psi_out = nullptr;
   return a;
 }
 
@@ -667,7 +667,7 @@ int set_state_of(lbsc_ctx* c, Member* mm, const void* host, size_t bytes) {
 // Workspace layout of the adjoint for a single box (lattices sized for the
 // largest padding so any tuning of the box fits).
 struct AdjLayout {
-  size_t lat, rho, cp, ring, rhos, P, R, psi_fbar, fbar_dot_v, partial, acc, total;
+  size_t lat, psi, cp, ring, psis, P, R, psi_fbar, fbar_dot_v, partial, acc, total;
   int ncp;
 };
 
@@ -677,17 +677,17 @@ AdjLayout adj_layout(const lbsc_params& p, int64_t nsteps, int32_t segment) {
   a.n = nodes(p);
   L.ncp = (int)((nsteps + segment - 1) / segment);
   L.lat = lattice_bytes(p, kMaxPad);
-  L.rho = align_up((size_t)a.n * elem_size(p));
+  L.psi = align_up((size_t)a.n * elem_size(p));
   L.cp = (size_t)L.ncp * L.lat;
   L.ring = (size_t)(segment + 1) * L.lat;
-  L.rhos = (size_t)segment * L.rho;
+  L.psis = (size_t)segment * L.psi;
   L.P = 2 * L.lat;
-  L.R = 2 * L.rho;
+  L.R = 2 * L.psi;
   L.psi_fbar = align_up(3 * (size_t)a.n * elem_size(p));
   L.fbar_dot_v = align_up((size_t)a.n * elem_size(p));
   L.partial = align_up(4 * sizeof(double) * (size_t)lbsc::adj_blocks(a));
   L.acc = kAlign;
-  L.total = L.cp + L.ring + L.rhos + L.P + L.R + L.psi_fbar + L.fbar_dot_v + L.partial + L.acc;
+  L.total = L.cp + L.ring + L.psis + L.P + L.R + L.psi_fbar + L.fbar_dot_v + L.partial + L.acc;
   return L;
 }
 
@@ -955,18 +955,18 @@ int lbsc_adjoint_forward(lbsc_ctx* c, int64_t nsteps, int32_t segment, void* wor
   w.segment = segment;
   w.ncp = L.ncp;
   w.lat_bytes = L.lat;
-  w.rho_bytes = L.rho;
+  w.psi_bytes = L.psi;
   w.cp = base;
   base += L.cp;
   w.ring = base;
   base += L.ring;
-  w.rho = base;
-  base += L.rhos;
+  w.psi = base;
+  base += L.psis;
   w.P[0] = base;
   w.P[1] = base + L.lat;
   base += L.P;
   w.R[0] = base;
-  w.R[1] = base + L.rho;
+  w.R[1] = base + L.psi;
   base += L.R;
   w.psi_fbar = base;
   base += L.psi_fbar;
@@ -1032,12 +1032,12 @@ int lbsc_adjoint_backward(lbsc_ctx* c, const double* rhobar_dev, double* rho0bar
   const size_t used = (size_t)lbsc::Q * mm.a.ps * elem_size(mm.p);
   for (int seg = w.ncp - 1; seg >= 0; --seg) {
     const int64_t len = std::min<int64_t>(w.segment, w.nsteps - (int64_t)seg * w.segment);
-    // Recompute the segment, keeping every lattice and density it uses.
+    // Recompute the segment, keeping every lattice and psi field it uses.
     HIP_OR_FAIL(c, hipMemcpyAsync(w.ring, w.cp + (size_t)seg * w.lat_bytes, used,
                                   hipMemcpyDeviceToDevice, c->stream));
     for (int64_t t = 0; t < len; ++t) {
       lbsc::StepArgs a2 = mm.a;
-      a2.rho_out = w.rho + (size_t)t * w.rho_bytes;
+      a2.psi_out = w.psi + (size_t)t * w.psi_bytes;
       HIP_OR_FAIL(c, lbsc::launch_step(prec, mm.p.collision, mm.p.forcing, c->tune.threads,
                                        c->tune.nodes_per_thread,
                                        w.ring + (size_t)t * w.lat_bytes,
@@ -1045,7 +1045,7 @@ int lbsc_adjoint_backward(lbsc_ctx* c, const double* rhobar_dev, double* rho0bar
     }
     for (int64_t t = len - 1; t >= 0; --t) {
       g.bprev = w.ring + (size_t)t * w.lat_bytes;
-      g.rho = w.rho + (size_t)t * w.rho_bytes;
+      g.psi = w.psi + (size_t)t * w.psi_bytes;
       g.p_next = w.P[pc];
       g.r_next = w.R[pc];
       g.p_out = w.P[pc ^ 1];

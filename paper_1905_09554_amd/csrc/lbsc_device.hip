@@ -533,14 +533,8 @@ __device__ inline void step_tile(const T* __restrict__ src, T* __restrict__ dst,
       sc_force<R>(q, ph.G, Fx, Fy, Fz);
       const unsigned idx =
           (unsigned)z * (unsigned)plane + (unsigned)((y0 + ly[k]) * nx + x0 + lx[k]);
-      if (a.rho_out) {
-        // The density psi was taken from (same sum order as for the LDS plane);
-        // the adjoint recomputation stores it for the force stencil.
-        R s = R(0);
-#pragma unroll
-        for (int q = 0; q < Q; ++q) s += cur[k][q];
-        static_cast<T*>(a.rho_out)[idx] = T(ph.rho_ref + s);
-      }
+      // The adjoint's recomputation keeps psi as the forces used it.
+      if (a.psi_out) static_cast<T*>(a.psi_out)[idx] = q.c;
       collide<R, COLL, FORC>(cur[k], Fx, Fy, Fz, ph);
       // Written once and read only in the next step: non-temporal stores keep
       // them from evicting the rows the neighbouring tiles still re-read.
@@ -1010,7 +1004,7 @@ __global__ void __launch_bounds__(256) k_adj_collide(AdjArgs g) {
   const StepArgs& a = g.a;
   const Phys<R> ph = make_phys<R>(a);
   const T* __restrict__ bprev = (const T*)g.bprev;
-  const T* __restrict__ rho = (const T*)g.rho;
+  const T* __restrict__ psi = (const T*)g.psi;
   const T* __restrict__ pn = (const T*)g.p_next;
   const T* __restrict__ rn = (const T*)g.r_next;
   T* __restrict__ po = (T*)g.p_out;
@@ -1020,35 +1014,39 @@ __global__ void __launch_bounds__(256) k_adj_collide(AdjArgs g) {
   if (i < a.n) {
     const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / a.plane);
     const Nbr nb = neighbours(x, y, z, a.nx, a.ny, a.nz, a.plane);
-    R f[Q], gb[Q];
-    pull<T, R>(bprev, a.ps, nb, f);
+    // The pulled populations stay in the storage type (exact; half the
+    // registers for float32) and are widened where they are used.
+    T f[Q];
+    R gb[Q];
+    pull<T, T>(bprev, a.ps, nb, f);
     // dL/dB_n(x)_b = P(x + c_b)_b + r(x + c_b)
     static_for<Q>([&](auto bc) {
       constexpr int b = decltype(bc)::value;
       const unsigned idx = nb.zo[1 + CZ[b]] + nb.yo[1 + CY[b]] + nb.xo[1 + CX[b]];
       gb[b] = R(pn[lat_index<T>(b, idx, a.ps)]) + R(rn[idx]);
     });
-    // Shan-Chen force at x from the density field of this step.
+    // Shan-Chen force at x from the psi field of this step (as the forward
+    // step computed it).
     R vx = R(0), vy = R(0), vz = R(0);
     static_for<Q - 1>([&](auto bc) {
       constexpr int b = decltype(bc)::value + 1;
       const unsigned idx = nb.zo[1 + CZ[b]] + nb.yo[1 + CY[b]] + nb.xo[1 + CX[b]];
-      const R wp = weight<R>(b) * psi_of(R(rho[idx]), ph.psi_rho0, ph.inv_psi_rho0);
+      const R wp = weight<R>(b) * R(psi[idx]);
       if constexpr (CX[b] != 0) vx += R(CX[b]) * wp;
       if constexpr (CY[b] != 0) vy += R(CY[b]) * wp;
       if constexpr (CZ[b] != 0) vz += R(CZ[b]) * wp;
     });
-    const R psi_c = psi_of(R(rho[i]), ph.psi_rho0, ph.inv_psi_rho0);
+    const R psi_c = R(psi[i]);
     const R gpsi = -ph.G * psi_c;
     const R Fx = gpsi * vx, Fy = gpsi * vy, Fz = gpsi * vz;
     // Forward moments (as in the collision).
     R s = R(0), jx = R(0), jy = R(0), jz = R(0);
     static_for<Q>([&](auto ac) {
       constexpr int q = decltype(ac)::value;
-      s += f[q];
-      if constexpr (CX[q] != 0) jx += R(CX[q]) * f[q];
-      if constexpr (CY[q] != 0) jy += R(CY[q]) * f[q];
-      if constexpr (CZ[q] != 0) jz += R(CZ[q]) * f[q];
+      s += R(f[q]);
+      if constexpr (CX[q] != 0) jx += R(CX[q]) * R(f[q]);
+      if constexpr (CY[q] != 0) jy += R(CY[q]) * R(f[q]);
+      if constexpr (CZ[q] != 0) jz += R(CZ[q]) * R(f[q]);
     });
     const R rr = ph.rho_ref + s;
     const R inv = R(1) / rr;
@@ -1080,7 +1078,7 @@ __global__ void __launch_bounds__(256) k_adj_collide(AdjArgs g) {
         // d f*/d omega = (f_eq - f) - S / 2
         const R geq = w * s + w * rr * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq);
         const R S = w * (R(3) * (cF - uF) + R(9) * cu * cF);
-        dom += gb[q] * (geq - f[q] - R(0.5) * S);
+        dom += gb[q] * (geq - R(f[q]) - R(0.5) * S);
       });
       sb = om * T0;
       rb = om * (Tq - R(1.5) * usq * T0);
@@ -1125,7 +1123,7 @@ __global__ void __launch_bounds__(256) k_adj_collide(AdjArgs g) {
             constexpr int q = decltype(ac)::value;
             if constexpr (mrt_entry(ii, q) != 0) {
               kb -= R(mrt_entry(ii, q)) * gb[q];
-              m += R(mrt_entry(ii, q)) * f[q];
+              m += R(mrt_entry(ii, q)) * R(f[q]);
             }
           });
           const R lam =
@@ -1252,7 +1250,7 @@ __global__ void __launch_bounds__(256) k_adj_psi(AdjArgs g) {
   using R = double;  // as in k_adj_collide
   const StepArgs& a = g.a;
   const Phys<R> ph = make_phys<R>(a);
-  const T* __restrict__ rho = (const T*)g.rho;
+  const T* __restrict__ psi = (const T*)g.psi;
   const T* __restrict__ t1v = (const T*)g.fbar_dot_v;
   const T* __restrict__ pfb = (const T*)g.psi_fbar;
   T* __restrict__ ro = (T*)g.r_out;
@@ -1270,8 +1268,8 @@ __global__ void __launch_bounds__(256) k_adj_psi(AdjArgs g) {
       if constexpr (CZ[b] != 0) ch += R(CZ[b]) * R(pfb[2 * a.n + im]);
       t2 += weight<R>(b) * ch;
     });
-    const R r = R(rho[i]);
-    const R dpsi = exp(-r * ph.inv_psi_rho0);
+    // psi' = exp(-rho / rho0) = 1 - psi / rho0.
+    const R dpsi = R(1) - R(psi[i]) * ph.inv_psi_rho0;
     ro[i] = T(-ph.G * (R(t1v[i]) + t2) * dpsi);
   }
 }

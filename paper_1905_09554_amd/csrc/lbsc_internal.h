@@ -45,7 +45,7 @@ struct StepArgs {
   int zchunk;         // planes per work-group
   int xcd_remap;      // 1: neighbouring tiles on one XCD
   double G, psi_rho0, tau, omega, s_bulk, s_ghost, rho_ref;
-  void* rho_out;      // if set, the step also writes the density it used (n values)
+  void* psi_out;      // if set, the step also writes the psi its forces used (n values)
 };
 
 // One member of a batch as the device sees it: its geometry and physics and
@@ -73,13 +73,14 @@ struct BatchLaunch {
 };
 
 // One adjoint step (see the adjoint section of lbsc_device.hip): lattice
-// B_{n-1}, density rho_n, adjoint (P, r) of step n+1 in, of step n out,
+// B_{n-1}, psi(rho_n) as step n computed it, adjoint (P, r) of step n+1 in,
+// of step n out,
 // dL/dF scratch (3n values) and per-block partials (4 doubles per block:
 // dL/dG, dL/dtau, dL/ds_bulk, dL/ds_ghost).
 struct AdjArgs {
   StepArgs a;
   const void* bprev;
-  const void* rho;
+  const void* psi;
   const void* p_next;
   const void* r_next;
   void* p_out;

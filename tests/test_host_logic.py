@@ -44,6 +44,17 @@ def test_autotune_candidates_are_valid_shapes():
     assert {336, 224, 112} <= widths
 
 
+def test_batch_autotune_candidates_are_valid_shapes():
+    from paper_1905_09554_amd import autotune
+    cands = autotune.batch_candidates()
+    assert len(cands) == len({tuple(sorted(c.items())) for c in cands})
+    for c in cands:
+        assert c["threads"] in (256, 512, 1024)
+        assert c["z_chunk"] >= 1 and c["xcd_remap"] in (0, 1) and c["persistent"] == 0
+    # the measured default (1024 threads, 8-plane chunks, plain order) is among them
+    assert dict(threads=1024, z_chunk=8, xcd_remap=0, persistent=0) in cands
+
+
 def test_growth_fit_recovers_an_exponential():
     from paper_1905_09554_amd import dispersion
     t = np.arange(0, 5000, 50.0)
