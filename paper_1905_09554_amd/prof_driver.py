@@ -68,8 +68,8 @@ def main():
     if args.batch:
         from paper_1905_09554_amd import dispersion
         sweep = dispersion.make_sweep(seed=0)
-        b = dispersion.build_batch(sweep)
-        b.step(args.steps)
+        b = dispersion.build_batch(sweep, persistent=0)  # one launch per step, also when
+        b.step(args.steps)                               # the tuned shape is persistent
         torch.cuda.synchronize()
         print("batch done", len(sweep["members"]), b.get_tuning(), flush=True)
         b.close()
