@@ -135,3 +135,25 @@ def test_batch_wide_and_narrow_members_bitwise(tuning):
         sim.close()
         assert np.array_equal(b.get_state(i), single), (i, tuning)
     b.close()
+
+
+def test_batch_autotune_candidates_bitwise():
+    """Every fourth launch shape the batch autotuner times (and the persistent
+    form of two of them) leaves every member bitwise equal to its single run."""
+    from paper_1905_09554_amd import autotune, lbsc
+    rhos, params = _members("f32", "bgk")
+    singles = []
+    for r, p in zip(rhos, params):
+        sim = lbsc.Simulation(r, p)
+        sim.step(9)
+        singles.append(sim.get_state()[0])
+        sim.close()
+    cands = autotune.batch_candidates()[::4]
+    cands += [dict(cands[0], persistent=1), dict(cands[-1], persistent=1)]
+    for shape in cands:
+        b = lbsc.Batch(rhos, params)
+        b.set_tuning(**shape)
+        b.step(9)
+        for i in range(len(rhos)):
+            assert np.array_equal(b.get_state(i), singles[i]), (i, shape)
+        b.close()
