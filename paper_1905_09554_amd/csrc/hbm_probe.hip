@@ -2,7 +2,7 @@
 // It is the denominator next to the 8 TB/s datasheet peak when the step's
 // achieved bandwidth is compared.  Prints one line per kernel and launch shape.
 //
-//   paper_1905_09554_amd/hbm_probe [gridstride|onepass|stream|lds|pull|shift|wide|lds19|all]
+//   paper_1905_09554_amd/hbm_probe [gridstride|onepass|stream|lds|pull|shift|wide|order|lds19|all]
 //
 // Families (every kernel moves a known number of bytes, timed over 10 launches
 // after a warm-up with HIP events):
@@ -30,6 +30,8 @@
 //              from aligned loads (checked to store what the plain form does);
 //  wide        the pull pattern with 2 or 4 consecutive nodes per lane (8- and
 //              16-byte accesses) against one node per lane;
+//  order       the pull pattern with its blocks of 1024 nodes in node order
+//              or in tile-major order (a group's march is one contiguous run);
 //  lds19       the same pattern with 16-byte direct global-to-LDS loads
 //              (pull_lds), and a 19-array stream with 16-byte accesses.
 #include <hip/hip_runtime.h>
@@ -241,6 +243,50 @@ pull_march(const float* __restrict__ src, float* __restrict__ dst, int nx, int n
     const unsigned i = (unsigned)z * plane + yo[1] + x;
 #pragma unroll
     for (int a = 0; a < 19; ++a) __builtin_nontemporal_store(cur[a] * 1.0001f, &dst[paddr<BLK>(a, i, ps)]);
+#pragma unroll
+    for (int a = 0; a < 19; ++a) cur[a] = nxt[a];
+  }
+}
+
+// The pull pattern in blocks of 1024 nodes (one 256 x 4 tile-plane each)
+// with the blocks in node order (TM = 0: block b = z * 64 + tile row) or in
+// tile-major order (TM = 1: block (tile row) * nz + z), so that a work-group's
+// march through the planes reads and writes one contiguous run of memory.
+template <int TM>
+__device__ inline size_t oaddr(int a, unsigned i, unsigned bpp, unsigned nz) {
+  unsigned b = i / 1024;
+  if (TM) b = (b % bpp) * nz + b / bpp;
+  return ((size_t)b * 19 + a) * 1024 + (i % 1024);
+}
+
+template <int TM>
+__global__ void __launch_bounds__(1024)
+pull_order(const float* __restrict__ src, float* __restrict__ dst, int nx, int ny, int nz,
+           int zc) {
+  const int tiles_y = ny / 4;
+  const int ty = blockIdx.x % tiles_y, chunk = blockIdx.x / tiles_y;
+  const int x = threadIdx.x % nx, y = ty * 4 + threadIdx.x / nx;
+  const int z0 = chunk * zc, z1 = z0 + zc;
+  const unsigned plane = (unsigned)nx * ny, bpp = plane / 1024;
+  const int xo[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
+  const int yo[3] = {(y == 0 ? ny - 1 : y - 1) * nx, y * nx, (y == ny - 1 ? 0 : y + 1) * nx};
+  float cur[19], nxt[19];
+  auto load = [&](int z, float(&v)[19]) {
+    const unsigned zo[3] = {(unsigned)(z == 0 ? nz - 1 : z - 1) * plane, (unsigned)z * plane,
+                            (unsigned)(z == nz - 1 ? 0 : z + 1) * plane};
+#pragma unroll
+    for (int a = 0; a < 19; ++a) {
+      const unsigned i = zo[1 - PCZ[a]] + yo[1 - PCY[a]] + xo[1 - PCX[a]];
+      v[a] = src[oaddr<TM>(a, i, bpp, (unsigned)nz)];
+    }
+  };
+  load(z0, cur);
+  for (int z = z0; z < z1; ++z) {
+    load(z + 1 < nz ? z + 1 : 0, nxt);
+    const unsigned i = (unsigned)z * plane + yo[1] + x;
+#pragma unroll
+    for (int a = 0; a < 19; ++a)
+      __builtin_nontemporal_store(cur[a] * 1.0001f, &dst[oaddr<TM>(a, i, bpp, (unsigned)nz)]);
 #pragma unroll
     for (int a = 0; a < 19; ++a) cur[a] = nxt[a];
   }
@@ -656,6 +702,24 @@ int main(int argc, char** argv) {
           one(std::integral_constant<int, 2>{}, std::integral_constant<int, 256>{}) ||
           one(std::integral_constant<int, 4>{}, std::integral_constant<int, 512>{}) ||
           one(std::integral_constant<int, 4>{}, std::integral_constant<int, 256>{}))
+        return 1;
+    }
+  }
+  if (want("order")) {
+    // Node-ordered against tile-major blocks (same box as the pull family).
+    const int nx = 256, ny = 256, nz = 512;
+    const size_t n = (size_t)nx * ny * nz;
+    const double traffic = 2.0 * 19 * n * 4;
+    for (int zc : {128, 32, 8}) {
+      const int grid = (ny / 4) * (nz / zc);
+      char name[32];
+      std::snprintf(name, sizeof(name), "pull_node_z%d", zc);
+      if (run(name, 1024, grid, traffic,
+              [&] { pull_order<0><<<grid, 1024>>>(a, b, nx, ny, nz, zc); }))
+        return 1;
+      std::snprintf(name, sizeof(name), "pull_tile_z%d", zc);
+      if (run(name, 1024, grid, traffic,
+              [&] { pull_order<1><<<grid, 1024>>>(a, b, nx, ny, nz, zc); }))
         return 1;
     }
   }
