@@ -331,8 +331,8 @@ def cpu_model():
 
 def host_threads():
     """Threads the oracle may use: the CPUs this process may run on, within
-    the OpenMP thread limit the host sets (the GPU machine grants each GPU a
-    share of its cores)."""
+    the OpenMP thread limit the environment sets (a shared host may grant
+    each GPU only a share of its cores)."""
     try:
         n = len(os.sched_getaffinity(0))
     except (AttributeError, OSError):
