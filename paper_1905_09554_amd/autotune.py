@@ -170,6 +170,8 @@ def tune_batch(workload=None, steps=5, progress=True, out=None):
         tried.append((t, shape))
         if progress:
             print("  %s: %s %.0f MLUPS" % (workload, shape, n / t / 1e6), flush=True)
+    if not tried:
+        raise RuntimeError("the library refused every batch launch shape")
     tried.sort(key=lambda x: x[0])
     finalists = [default_shape] + [shape for _, shape in tried[:4]]
     finalists.append(dict(tried[0][1], persistent=1))
