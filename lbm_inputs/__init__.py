@@ -228,5 +228,5 @@ def paper_ligament(R0, operator, eps=0.1, wavelengths=2):
     ly = 96 * R0 // 14
     rho = ligament_density(ly, ly, lx, float(R0), eps, wavelengths, t["rho_v"][i], t["rho_l"][i])
     return rho, {"R0": R0, "operator": operator, "eps": eps, "nx": ly, "ny": ly, "nz": lx,
-                 "G": PAPER_G0, "tau": t["tau"][i], "t_cap": t["t_cap"][i],
+                 "wavelengths": wavelengths, "G": PAPER_G0, "tau": t["tau"][i], "t_cap": t["t_cap"][i],
                  "rho_l": t["rho_l"][i], "rho_v": t["rho_v"][i], "sigma": t["sigma"][i]}

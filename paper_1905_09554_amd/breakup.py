@@ -76,9 +76,10 @@ class Recorder:
 
     * r(z, t), the equivalent radius of each slice (interface diagnostics);
       from it the minimum radius h_min(t) / R0 (Fig. 5) and the perturbation
-      at the neck z = L/4 and at the crest z = 0, each normalised by its
-      initial value (Fig. 4a: our cos profile puts the neck at L/4 where the
-      paper's sin profile has it at 3 L/8);
+      at the first neck z = nz / (2 m) of the m wavelengths in the box
+      (info["wavelengths"], default 2: L/4) and at the crest z = 0, each
+      normalised by its initial value (Fig. 4a: our cos profile puts the neck
+      at L/4 where the paper's sin profile has it at 3 L/8);
     * silhouettes r(z) at the requested t* = t / t_cap (Fig. 4b: 7, 8, 9);
     * v* = |u^b| / (R0 / t_cap) on the plane through the axis (y = ny/2) at
       the requested t* (Fig. 6), float32 [nz, nx].
@@ -115,7 +116,7 @@ class Recorder:
         t = np.asarray(self.t, dtype=np.float64)
         nz = r.shape[1]
         rbar = r[0].mean()
-        neck, crest = nz // 4, 0
+        neck, crest = nz // (2 * info.get("wavelengths", 2)), 0
         return {
             "t_star": t / info["t_cap"],
             "h_min_over_R0": r.min(axis=1) / info["R0"],

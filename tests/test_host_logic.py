@@ -73,8 +73,9 @@ def test_mode_amplitude_of_a_cosine():
 
 
 class _FakeSim:
-    """Stands in for lbsc.Simulation: a radius profile that narrows at the
-    neck z = nz/4 and a uniform velocity field."""
+    """Stands in for lbsc.Simulation: a radius profile of m wavelengths
+    (info["wavelengths"], default 2) that narrows at the necks z = nz/(2m)
+    (2k + 1) and a uniform velocity field."""
 
     def __init__(self, info):
         self.info = info
@@ -82,9 +83,10 @@ class _FakeSim:
 
     def diagnostics(self, rho_v, rho_l):
         nz = self.info["nz"]
+        m = self.info.get("wavelengths", 2)
         z = np.arange(nz)
         amp = 1.0 + 0.1 * self.k
-        r = self.info["R0"] * (1.0 + 0.1 * amp * np.cos(4 * math.pi * z / nz))
+        r = self.info["R0"] * (1.0 + 0.1 * amp * np.cos(2 * m * math.pi * z / nz))
         return {"r_of_z": r}
 
     def moments(self, want_u=True, want_p=False):
@@ -113,6 +115,23 @@ def test_recorder_bookkeeping():
     assert st == 150 and v.shape == (64, 8)
     assert np.allclose(v, 0.01 / (14 / 100.0))
     assert abs(r["h_min_over_R0"][0] - 0.9) < 1e-12
+
+
+def test_recorder_neck_of_a_one_wavelength_box():
+    """With one wavelength in the box the neck is the middle slice."""
+    from paper_1905_09554_amd import breakup
+    info = {"nx": 8, "ny": 8, "nz": 64, "R0": 14, "t_cap": 100.0, "rho_v": 0.08, "rho_l": 2.1,
+            "wavelengths": 1}
+    rec = breakup.Recorder(info, silhouette_tstar=(), velocity_tstar=())
+    sim = _FakeSim(info)
+    for k in range(0, 11):
+        sim.k = k
+        rec.sample(sim, 10 * k)
+    r = rec.result()
+    assert np.allclose(r["neck_perturbation"], 1.0 + 0.1 * np.arange(11))
+    assert np.allclose(r["crest_perturbation"], 1.0 + 0.1 * np.arange(11))
+    _, info2 = lbm_inputs.paper_ligament(14, "mrt", wavelengths=1)
+    assert info2["wavelengths"] == 1 and info2["nz"] == 128
 
 
 def test_droplet_and_slab_inputs():
