@@ -164,7 +164,8 @@ int lbsc_interface_diagnostics(lbsc_ctx* c, double rho_v, double rho_l, lbsc_dia
  * library instead of the context's buffer.  Same arguments, kernels and
  * results (bitwise) as lbsc_interface_diagnostics; the density and psi fields
  * still use the context's idle lattice, as there.  Calls no hipMalloc,
- * hipFree or other allocating routine.
+ * hipFree or other allocating routine, and takes no host heap memory except
+ * for the message of an error it returns.
  *   Limit: the array holds 16 MiB per GPU, for the life of the process; a box
  *   needs nz * ceil(nx * ny / 4096) * 64 bytes of partials plus
  *   (4 + nz) * 8 bytes of results (rounded up to 256 bytes), so e.g.

@@ -605,29 +605,46 @@ int diagnostics_into(lbsc_ctx* c, Member* mm, double rho_v, double rho_l, lbsc_d
                                           (double*)mm->lat[c->cur ^ 1], part, dres, rho_v,
                                           rho_l, mm->a, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "diagnostics launch");
-  std::vector<double> h(4 + (size_t)nz);
-  HIP_OR_FAIL(c, hipMemcpyAsync(h.data(), dres, h.size() * sizeof(double),
-                                hipMemcpyDeviceToHost, c->stream));
+  // No heap memory on this path (the static-scratch entry point allocates
+  // nothing): the four sums go to the stack, the slice areas A(z) to the
+  // caller's r_of_z buffer (turned into radii in place) or, without one,
+  // through a stack buffer a chunk at a time.
+  double head[4];
+  HIP_OR_FAIL(c, hipMemcpyAsync(head, dres, sizeof(head), hipMemcpyDeviceToHost, c->stream));
+  if (r_of_z_host)
+    HIP_OR_FAIL(c, hipMemcpyAsync(r_of_z_host, dres + 4, (size_t)nz * sizeof(double),
+                                  hipMemcpyDeviceToHost, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
-  out->mass = h[0];
-  out->mom[0] = h[1];
-  out->mom[1] = h[2];
-  out->mom[2] = h[3];
+  out->mass = head[0];
+  out->mom[0] = head[1];
+  out->mom[1] = head[2];
+  out->mom[2] = head[3];
   out->reserved = 0;
   const double pi = 3.14159265358979323846;
   double rmin = INFINITY;
   int zmin = 0;
-  for (int z = 0; z < nz; ++z) {
-    const double r = std::sqrt(h[4 + z] / pi);
-    if (r_of_z_host) r_of_z_host[z] = r;
-    if (r < rmin) {
-      rmin = r;
-      zmin = z;
+  constexpr int kChunk = 256;
+  double tmp[kChunk];
+  for (int z0 = 0; z0 < nz; z0 += kChunk) {
+    const int len = std::min(kChunk, nz - z0);
+    double* a = r_of_z_host ? r_of_z_host + z0 : tmp;
+    if (!r_of_z_host) {
+      HIP_OR_FAIL(c, hipMemcpyAsync(tmp, dres + 4 + z0, (size_t)len * sizeof(double),
+                                    hipMemcpyDeviceToHost, c->stream));
+      HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    }
+    for (int k = 0; k < len; ++k) {
+      const double r = std::sqrt(a[k] / pi);
+      a[k] = r;
+      if (r < rmin) {
+        rmin = r;
+        zmin = z0 + k;
+      }
     }
   }
   out->r_min = rmin;
   out->z_argmin = zmin;
-  if (!std::isfinite(h[0])) return fail(&c->err, LBSC_ENONFINITE, "mass is not finite");
+  if (!std::isfinite(head[0])) return fail(&c->err, LBSC_ENONFINITE, "mass is not finite");
   return LBSC_OK;
 }
 
