@@ -41,7 +41,7 @@ BYTES_PER_NODE = {"f32": 19 * 2 * 4, "f64": 19 * 2 * 8}
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("lbsc_device.hip", "lbsc_api.hip"):
+    for name in ("lbsc_device.hip", "lbsc_api.hip", "lbsc_internal.h"):
         with open(os.path.join(ROOT, "paper_1905_09554_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

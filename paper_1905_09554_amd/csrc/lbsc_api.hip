@@ -12,8 +12,10 @@
 //   [member 0: lattice 0 | lattice 1] [member 1: ...] ... [aux]
 //   aux = member table | tile table | barrier words | diagnostic partials |
 //         diagnostic results
-// A single box reserves room for a population padding of up to kMaxPad so
-// its layout can be retuned in place; batch members use the default pad.
+// With one array per population (a layout block of 0), a single box reserves
+// room for a padding of up to kMaxPad between the arrays so its layout can be
+// retuned in place, and batch members use the default pad; with populations
+// in blocks (the layout of both storage types) there is no padding.
 #include "lbsc.h"
 
 #include <hip/hip_runtime.h>
@@ -278,7 +280,8 @@ void chunk_and_order(const lbsc_params* p, int32_t n, lbsc_tuning* t) {
   const long long groups = one_wave ? 256 : 512;
   // Batches: chunks of at most 8 planes (the 64-ligament sweep: 13.87 ms per
   // step against 14.24 with 64-plane chunks, about 50 000 short-lived groups
-  // whose tail wave is a small fraction of the step).
+  // whose tail wave is a small fraction of the step; with the populations in
+  // blocks the batch autotuner finds 32-plane chunks a few per cent faster).
   const long long zmax = one_wave ? 256 : (n > 1 ? 8 : 64);
   long long zc = (columns + groups - 1) / groups;
   if (zc < 1) zc = 1;

@@ -17,13 +17,14 @@
 // and every formula below is written for g (rho_ref = 0 gives plain f).
 //
 // The hot kernel fuses streaming, moments, psi, the force gather, forcing
-// and collision.  A work-group owns full x-rows [y0, y0 + by) and marches a
-// chunk of z planes.  For each plane it pulls the populations of its tile
-// plus one halo row on each side, reduces them to psi and keeps psi in a
-// ring of four LDS planes; the interior populations stay in registers for the
-// collision one plane later.  Each node therefore reads its 19 populations
-// from HBM once and writes 19; the halo rows are re-reads that hit L2 when
-// the neighbouring tile (placed on the same XCD) has just loaded them.
+// and collision.  A work-group owns a tile of bx columns by by rows (whole
+// rows where they fit) and marches a chunk of z planes.  For each plane it
+// pulls the populations of its tile plus a one-node halo ring, reduces them
+// to psi and keeps psi in a ring of four LDS planes; the interior
+// populations stay in registers for the collision one plane later.  Each
+// node therefore reads its 19 populations from HBM once and writes 19; the
+// halo ring is re-read, mostly from L2 when the neighbouring tile (placed on
+// the same XCD) has just loaded it.
 #include "lbsc_internal.h"
 
 #include <hip/hip_runtime.h>

@@ -10,7 +10,7 @@ Both counters are in KiB per dispatch.  Each is scaled by what it reads for
 the driver's plain copy of a known size (1 GiB read, 1 GiB written), and the
 per-launch bytes of the step kernel are written to
 profiles/traffic_<workload>_<precision>.json together with a hash of the
-kernel sources and the autotuner's launch shape for the box (the benchmark
+kernel sources (lbsc_device.hip, lbsc_api.hip, lbsc_internal.h) and the autotuner's launch shape for the box (the benchmark
 ignores the file once either changes).
 """
 import argparse
