@@ -1,7 +1,7 @@
 """Writes the oracle's expected values for the full-size parity windows.
 
 Calls only the oracle (float64 CPU) and the input builder.  Run from the
-repository root (about an hour on 8 cores, 20 GB of memory):
+repository root (10-25 minutes per case on 8 cores, up to 20 GB of memory):
 
     python tests/golden/make_fullsize.py [case ...]
 
@@ -11,6 +11,11 @@ Cases (the ligament inputs of lbm_inputs.WORKLOADS, seed 0):
                   U(+-1e-4); 200 steps of the whole box (one step couples
                   nodes up to two links apart, so 200 steps reach every plane
                   of the 512-plane box).
+  c2_srt_shift    the same box and input, BGK with the velocity-shift forcing
+                  (the paper's SRT operator), tau = 1; 200 steps, whole box.
+  c2_mrt_paper    the same box and input, MRT with the paper's rate set
+                  (shear and bulk 1/tau, every other rate 1), tau = 0.8;
+                  200 steps, whole box.
   c3_mrt          256 x 256 x 1024 MRT, R = 64, kR_eff = 0.785, noise U(+-1e-4);
                   50 steps.  After k steps a node depends only on the nodes
                   within 2k links, so the oracle runs the slab of planes
@@ -45,7 +50,19 @@ CASES = {
                    slab=None, stride=2),
     "c3_mrt": dict(workload="ligament_256x256x1024_mrt_f32", collision="mrt", steps=50, z0=256,
                    slab=104, stride=4),
+    "c2_srt_shift": dict(workload="ligament_128x128x512", collision="bgk", forcing="shift",
+                         steps=200, z0=128, slab=None, stride=2),
+    "c2_mrt_paper": dict(workload="ligament_128x128x512", collision="mrt", tau=0.8,
+                         s_bulk=1.0 / 0.8, s_ghost=1.0, steps=200, z0=128, slab=None, stride=2),
 }
+
+
+def case_params(c, info):
+    """The oracle's parameters of case c (the workload's G and tau unless the
+    case sets its own; MRT ghost 1.2 and bulk 1.0 unless set)."""
+    return lbm.Params(G=info["G"], tau=c.get("tau", info["tau"]), collision=c["collision"],
+                      forcing=c.get("forcing", "guo"), s_bulk=c.get("s_bulk", 1.0),
+                      s_ghost=c.get("s_ghost", 1.2))
 
 
 def sample_nodes(nx, ny, stride):
@@ -67,8 +84,7 @@ def run_case(name):
         zl = c["slab"]
     else:
         zl = z0
-    p = lbm.Params(G=info["G"], tau=info["tau"], collision=c["collision"], s_bulk=1.0,
-                   s_ghost=1.2)
+    p = case_params(c, info)
     t = time.time()
     f = lbm.init_rest(torch.from_numpy(rho0))
     del rho0
@@ -82,7 +98,9 @@ def run_case(name):
     ys, xs = sample_nodes(nx, ny, c["stride"])
     out = os.path.join(ROOT, "tests", "golden", "fullsize_%s.npz" % name)
     np.savez(out, z0=np.int64(z0), y=ys, x=xs, rho=rho.numpy()[ys, xs],
-             u=ub.numpy()[:, ys, xs], steps=np.int64(c["steps"]))
+             u=ub.numpy()[:, ys, xs], steps=np.int64(c["steps"]), tau=np.float64(p.tau),
+             s_bulk=np.float64(p.s_bulk), s_ghost=np.float64(p.s_ghost),
+             forcing=np.str_(p.forcing))
     print("wrote", out, flush=True)
 
 

@@ -11,7 +11,7 @@ from tests import gpu_cases as gc
 pytestmark = pytest.mark.gpu
 
 
-def _members(precision, collision):
+def _members(precision, collision, forcing="guo"):
     from paper_1905_09554_amd import lbsc
     rv, rl = lbm_inputs.coexistence(-5.0)
     specs = [(32, 32, 50, 8.0, 1.0), (44, 44, 37, 11.0, 0.8), (24, 24, 60, 6.0, 0.9),
@@ -20,8 +20,8 @@ def _members(precision, collision):
     for nx, ny, nz, R, tau in specs:
         rhos.append(lbm_inputs.ligament_density(nx, ny, nz, R, 0.05, 1, rv, rl, noise=1e-4,
                                                 seed=nx))
-        params.append(lbsc.make_params(nx, ny, nz, collision=collision, precision=precision,
-                                       G=-5.0, tau=tau))
+        params.append(lbsc.make_params(nx, ny, nz, collision=collision, forcing=forcing,
+                                       precision=precision, G=-5.0, tau=tau))
     return rhos, params
 
 
@@ -38,6 +38,24 @@ def test_batch_members_equal_single_runs_bitwise(precision, collision, persisten
     for i, (r, p) in enumerate(zip(rhos, params)):
         sim = lbsc.Simulation(r, p)
         sim.step(13)
+        single, _ = sim.get_state()
+        sim.close()
+        assert np.array_equal(b.get_state(i), single), i
+    b.close()
+
+
+@pytest.mark.parametrize("persistent", [0, 1])
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_batch_velocity_shift_members_equal_single_runs_bitwise(precision, persistent):
+    """The paper's SRT operator (BGK with the velocity shift) in a batch."""
+    from paper_1905_09554_amd import lbsc
+    rhos, params = _members(precision, "bgk", forcing="shift")
+    b = lbsc.Batch(rhos, params)
+    b.set_tuning(persistent=persistent)
+    b.step(11)
+    for i, (r, p) in enumerate(zip(rhos, params)):
+        sim = lbsc.Simulation(r, p)
+        sim.step(11)
         single, _ = sim.get_state()
         sim.close()
         assert np.array_equal(b.get_state(i), single), i

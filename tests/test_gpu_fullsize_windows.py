@@ -1,7 +1,8 @@
 """Full-size parity windows against the oracle, in the launch configuration
-the benchmark uses: the 128 x 128 x 512 ligament over 200 steps (BGK and MRT)
-and the 256 x 256 x 1024 MRT ligament over 50 steps, each in float64 and in
-float32 shifted storage.
+the benchmark uses: the 128 x 128 x 512 ligament over 200 steps (BGK and MRT
+with Guo forcing, and the paper's two operators: BGK with the velocity shift,
+MRT with its rate set) and the 256 x 256 x 1024 MRT ligament over 50 steps,
+each in float64 and in float32 shifted storage.
 
 The expected values are the oracle's, written by tests/golden/make_fullsize.py
 (the whole 128 x 128 x 512 box; for 256 x 256 x 1024 a slab of 208 planes
@@ -29,6 +30,8 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 CASES = {
     "c2_bgk": ("ligament_128x128x512", "bgk"),
     "c2_mrt": ("ligament_128x128x512", "mrt"),
+    "c2_srt_shift": ("ligament_128x128x512", "bgk"),
+    "c2_mrt_paper": ("ligament_128x128x512", "mrt"),
     "c3_mrt": ("ligament_256x256x1024_mrt_f32", "mrt"),
 }
 
@@ -44,8 +47,18 @@ def test_full_size_window_against_oracle(case, prec):
     nz, ny, nx = rho0.shape
     print("full-size window %s %s %s: %d steps, plane %d, %d sampled nodes"
           % (case, workload, prec, steps, z0, ref["rho"].size), flush=True)
-    prm = lbsc.make_params(nx, ny, nz, collision=coll, precision=prec, G=info["G"],
-                           tau=info["tau"], s_bulk=1.0, s_ghost=1.2)
+    if "forcing" in ref.files:
+        print("  forcing %s, tau %g, s_bulk %g, s_ghost %g" % (ref["forcing"], ref["tau"],
+                                                             ref["s_bulk"], ref["s_ghost"]),
+              flush=True)
+    # Forcing, tau and MRT rates as the oracle ran them (stored with its values;
+    # files without them used Guo forcing, the workload's tau, bulk 1.0, ghost 1.2).
+    forcing = str(ref["forcing"]) if "forcing" in ref.files else "guo"
+    tau = float(ref["tau"]) if "tau" in ref.files else info["tau"]
+    s_bulk = float(ref["s_bulk"]) if "s_bulk" in ref.files else 1.0
+    s_ghost = float(ref["s_ghost"]) if "s_ghost" in ref.files else 1.2
+    prm = lbsc.make_params(nx, ny, nz, collision=coll, forcing=forcing, precision=prec,
+                           G=info["G"], tau=tau, s_bulk=s_bulk, s_ghost=s_ghost)
     sim = lbsc.Simulation(rho0, prm)
     tuning.apply(sim, prm)
     sim.step(steps)
