@@ -150,6 +150,22 @@ def test_ragged_shapes_f64(shape, tuning, coll):
     assert float(np.abs(g["state"] - o["state"]).max()) < F64_TOL
 
 
+@pytest.mark.parametrize("tau", [0.55, 2.0])
+@pytest.mark.parametrize("coll,forcing", [("bgk", "guo"), ("mrt", "guo"), ("bgk", "shift")])
+def test_relaxation_time_extremes_f64(coll, forcing, tau):
+    """tau near its lower bound 1/2 (little viscosity) and large (strong
+    damping) on a ligament, 100 steps, every population against the oracle;
+    MRT with ghost rate 1.9 next to the small tau."""
+    rho0 = gc.ligament(24, 24, 32, 6.0, 0.1, 1, noise=1e-4, seed=3)
+    s_ghost = 1.9 if tau < 1 else 1.2
+    g = gc.run_gpu(rho0, 100, collision=coll, forcing=forcing, tau=tau, s_ghost=s_ghost)
+    o = gc.run_oracle(rho0, 100, collision=coll, forcing=forcing, tau=tau, s_ghost=s_ghost)
+    assert np.isfinite(o["state"]).all()
+    err = float(np.abs(g["state"] - o["state"]).max())
+    print("%s %s tau %.2f: max |df| %.3e" % (coll, forcing, tau, err), flush=True)
+    assert err < F64_TOL
+
+
 _SHAPES_40 = (None, dict(threads=256, z_chunk=3), dict(threads=512, block_y=1, z_chunk=30),
               dict(threads=1024, xcd_remap=0, z_chunk=4), dict(threads=1024, block_y=5),
               dict(threads=256, nodes_per_thread=2, z_chunk=6),
