@@ -2,7 +2,7 @@
 // It is the denominator next to the 8 TB/s datasheet peak when the step's
 // achieved bandwidth is compared.  Prints one line per kernel and launch shape.
 //
-//   paper_1905_09554_amd/hbm_probe [gridstride|onepass|stream|lds|pull|shift|wide|order|lds19|all]
+//   paper_1905_09554_amd/hbm_probe [gridstride|onepass|stream|lds|pull|shift|wide|order|pull64|lds19|all]
 //
 // Families (every kernel moves a known number of bytes, timed over 10 launches
 // after a warm-up with HIP events):
@@ -32,6 +32,8 @@
 //              16-byte accesses) against one node per lane;
 //  order       the pull pattern with its blocks of 1024 nodes in node order
 //              or in tile-major order (a group's march is one contiguous run);
+//  pull64      the pull pattern on float64 populations, tiles as the float64
+//              step uses them and wider;
 //  lds19       the same pattern with 16-byte direct global-to-LDS loads
 //              (pull_lds), and a 19-array stream with 16-byte accesses.
 #include <hip/hip_runtime.h>
@@ -243,6 +245,44 @@ pull_march(const float* __restrict__ src, float* __restrict__ dst, int nx, int n
     const unsigned i = (unsigned)z * plane + yo[1] + x;
 #pragma unroll
     for (int a = 0; a < 19; ++a) __builtin_nontemporal_store(cur[a] * 1.0001f, &dst[paddr<BLK>(a, i, ps)]);
+#pragma unroll
+    for (int a = 0; a < 19; ++a) cur[a] = nxt[a];
+  }
+}
+
+// The pull pattern on float64 populations (blocks of 1024 nodes): tiles of
+// BX columns by NT / BX rows, as the float64 step uses (64 x 4 tiles of 256
+// threads by default), each thread pulling the 19 values of its node.
+template <int NT, int BX>
+__global__ void __launch_bounds__(NT)
+pull_march64(const double* __restrict__ src, double* __restrict__ dst, int nx, int ny, int nz,
+             int zc) {
+  constexpr int BY = NT / BX;
+  const int ntx = nx / BX, nty = ny / BY;
+  const int tile = blockIdx.x % (ntx * nty), chunk = blockIdx.x / (ntx * nty);
+  const int x = (tile % ntx) * BX + (int)threadIdx.x % BX;
+  const int y = (tile / ntx) * BY + (int)threadIdx.x / BX;
+  const int z0 = chunk * zc, z1 = z0 + zc;
+  const unsigned plane = (unsigned)nx * ny;
+  const int xo[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
+  const int yo[3] = {(y == 0 ? ny - 1 : y - 1) * nx, y * nx, (y == ny - 1 ? 0 : y + 1) * nx};
+  double cur[19], nxt[19];
+  auto load = [&](int z, double(&v)[19]) {
+    const unsigned zo[3] = {(unsigned)(z == 0 ? nz - 1 : z - 1) * plane, (unsigned)z * plane,
+                            (unsigned)(z == nz - 1 ? 0 : z + 1) * plane};
+#pragma unroll
+    for (int a = 0; a < 19; ++a) {
+      const unsigned i = zo[1 - PCZ[a]] + yo[1 - PCY[a]] + xo[1 - PCX[a]];
+      v[a] = src[paddr<1024>(a, i, 0)];
+    }
+  };
+  load(z0, cur);
+  for (int z = z0; z < z1; ++z) {
+    load(z + 1 < nz ? z + 1 : 0, nxt);
+    const unsigned i = (unsigned)z * plane + yo[1] + x;
+#pragma unroll
+    for (int a = 0; a < 19; ++a)
+      __builtin_nontemporal_store(cur[a] * 1.0001, &dst[paddr<1024>(a, i, 0)]);
 #pragma unroll
     for (int a = 0; a < 19; ++a) cur[a] = nxt[a];
   }
@@ -720,6 +760,32 @@ int main(int argc, char** argv) {
       std::snprintf(name, sizeof(name), "pull_tile_z%d", zc);
       if (run(name, 1024, grid, traffic,
               [&] { pull_order<1><<<grid, 1024>>>(a, b, nx, ny, nz, zc); }))
+        return 1;
+    }
+  }
+  if (want("pull64")) {
+    // float64 populations: 256 x 256 x 256 box, 19 x 8 B x n = 2.55 GB.
+    const int nx = 256, ny = 256, nz = 256;
+    const size_t n = (size_t)nx * ny * nz;
+    const double traffic = 2.0 * 19 * n * 8;
+    double* a8 = reinterpret_cast<double*>(a);
+    double* b8 = reinterpret_cast<double*>(b);
+    for (int zc : {64, 16, 4}) {
+      char name[40];
+      auto one = [&](auto tc, auto bc) -> int {
+        constexpr int T = decltype(tc)::value, BX = decltype(bc)::value;
+        const int grid = (nx / BX) * (ny / (T / BX)) * (nz / zc);
+        std::snprintf(name, sizeof(name), "pull64_t%d_%dx%d_z%d", T, BX, T / BX, zc);
+        return run(name, T, grid, traffic,
+                   [&] { pull_march64<T, BX><<<grid, T>>>(a8, b8, nx, ny, nz, zc); });
+      };
+      using I256 = std::integral_constant<int, 256>;
+      using I512 = std::integral_constant<int, 512>;
+      using I1024 = std::integral_constant<int, 1024>;
+      using I64 = std::integral_constant<int, 64>;
+      using I128 = std::integral_constant<int, 128>;
+      if (one(I256{}, I64{}) || one(I256{}, I256{}) || one(I512{}, I128{}) ||
+          one(I512{}, I256{}) || one(I1024{}, I256{}))
         return 1;
     }
   }
